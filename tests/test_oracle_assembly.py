@@ -211,10 +211,13 @@ def test_nonpositive_jacobian_rejected():
 def test_sinprod_rhs_converges_to_its_solution(rng):
     # f = d pi^2 prod sin(pi x_i) has u = prod sin(pi x_i); the p = 3 discrete
     # solution on 8 elements is within the interpolation error of u
-    prob = synth.uniform_problem(2, 8, 3)
-    A = assembly.assemble_matrix(prob)
-    b = assembly.assemble_load(prob, synth.RHS_SINPROD)
-    u = np.linalg.solve(A.toarray(), b)
     pts = rng.random((40, 2))
-    err = np.abs(_evaluate(prob, u, pts) - np.prod(np.sin(np.pi * pts), axis=1)).max()
-    assert err < 2e-5
+    errs = []
+    for E in (8, 16):
+        prob = synth.uniform_problem(2, E, 3)
+        A = assembly.assemble_matrix(prob)
+        b = assembly.assemble_load(prob, synth.RHS_SINPROD)
+        u = np.linalg.solve(A.toarray(), b)
+        errs.append(np.abs(_evaluate(prob, u, pts) - np.prod(np.sin(np.pi * pts), axis=1)).max())
+    assert errs[0] < 1e-4
+    assert errs[0] / errs[1] > 10  # order p+1 = 4 convergence
