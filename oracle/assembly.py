@@ -150,9 +150,11 @@ def assemble_matrix(problem, rows=None, chunk=None):
         if np.any(det <= 0):
             raise ValueError("det J <= 0 at a quadrature point")
         Q = Q.reshape(C, T, d, d)
-        # A^e_ab = sum_t w_t sum_ij grad_i B_a(t) Q_ij(t) grad_j B_b(t)
-        QG = np.einsum("etij,ejtb->etib", Q, grads)
-        Ae = np.einsum("et,eita,etib->eab", w, grads, QG)
+        # A^e_ab = sum_t w_t sum_ij grad_i B_a(t) Q_ij(t) grad_j B_b(t), written as
+        # two batched matrix products (library matmul) over the same sum
+        G = np.swapaxes(grads, 1, 2)                     # (C, T, d, L): grad_i B_a(t)
+        QG = np.matmul(Q, G) * w[:, :, None, None]       # (C, T, d, L): w_t sum_j Q_ij grad_j B_b
+        Ae = np.matmul(np.swapaxes(G.reshape(C, T * d, -1), 1, 2), QG.reshape(C, T * d, -1))
         r = np.broadcast_to(dofs[:, :, None], Ae.shape)
         c = np.broadcast_to(dofs[:, None, :], Ae.shape)
         ok = (r >= 0) & (c >= 0)

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) fast-diagonalisation preconditioned CG for isogeometric
+Poisson problems (Sangalli & Tani, arXiv 1602.01636).
+
+The solver lives in the HIP library libigafd.so (C ABI in include/igafd.h);
+`binding` marshals arguments to it.  Importing this package does not load the
+library; the first igafd_* call does, and fails loudly when it is not built.
+"""
+from .binding import (IgafdError, Context, igafd_apply_A, igafd_apply_precond, igafd_destroy, igafd_diagonals,
+                      igafd_get_eigen, igafd_last_error, igafd_load_vector, igafd_set_scaling, igafd_setup,
+                      igafd_sizes, igafd_solve, igafd_univariate, lib)
+
+__all__ = ["IgafdError", "Context", "igafd_apply_A", "igafd_apply_precond", "igafd_destroy", "igafd_diagonals",
+           "igafd_get_eigen", "igafd_last_error", "igafd_load_vector", "igafd_set_scaling", "igafd_setup",
+           "igafd_sizes", "igafd_solve", "igafd_univariate", "lib"]

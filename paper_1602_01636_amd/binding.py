@@ -1,0 +1,276 @@
+"""Thin ctypes binding of the C ABI declared in include/igafd.h.
+
+Argument marshalling only: every step of the solver runs in libigafd.so.
+Functions keep the C names.  Vectors are torch float64 CUDA tensors,
+contiguous, N = prod(n) elements laid out as [n3][n2][n1] (direction 1
+fastest).  Calls are ordered on the stream passed to igafd_setup (default: the
+current torch stream).  A non-OK status raises IgafdError with the library's
+message; there is no fallback when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigafd.so")
+
+IGAFD_OK, IGAFD_NOT_CONVERGED = 0, 1
+IGAFD_FP64, IGAFD_FP32, IGAFD_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": IGAFD_FP64, "fp32": IGAFD_FP32, "bf16": IGAFD_BF16}
+GEOM_KINDS = {"identity": 0, "ring": 1, "warped": 2}
+COEF_KINDS = {"one": 0, "sincos": 1}
+RHS_KINDS = {"sinprod": 0, "paper_poly": 1, "bubble": 2, "one": 3}
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_ALLOC", -3: "ERR_HIP",
+                -4: "ERR_GEOMETRY", -5: "ERR_NOT_SPD", -6: "ERR_BREAKDOWN"}
+
+
+class IgafdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class igafd_problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("nknots", C.c_int * 3),
+                ("knots", C.POINTER(C.c_double) * 3), ("geom_kind", C.c_int), ("n_geom_params", C.c_int),
+                ("geom_params", C.POINTER(C.c_double)), ("coef_kind", C.c_int), ("n_coef_params", C.c_int),
+                ("coef_params", C.POINTER(C.c_double)), ("quad_per_dir", C.c_int)]
+
+
+class igafd_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("flexible", C.c_int),
+                ("use_scaling", C.c_int), ("check_every", C.c_int), ("use_x0", C.c_int),
+                ("history", C.POINTER(C.c_double))]
+
+
+class igafd_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("relres", C.c_double), ("true_relres", C.c_double),
+                ("status", C.c_int), ("t_solve_ms", C.c_double)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "igafd_setup": (C.c_int, [C.POINTER(igafd_problem), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "igafd_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
+                              C.POINTER(C.c_longlong)]),
+    "igafd_load_vector": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "igafd_apply_A": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "igafd_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "igafd_set_scaling": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(igafd_solve_opts),
+                              C.POINTER(igafd_solve_info)]),
+    "igafd_diagonals": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "igafd_get_eigen": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "igafd_univariate": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]),
+    "igafd_destroy": (None, [C.c_void_p]),
+    "igafd_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libigafd.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def igafd_last_error() -> str:
+    return lib().igafd_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise IgafdError(status, igafd_last_error())
+    return status
+
+
+def _dptr(t, N=None, name="vector"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if N is not None and t.numel() != N:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {N}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def geometry_params(geom: dict, dim: int):
+    kind = GEOM_KINDS[geom["kind"]]
+    if geom["kind"] != "warped":
+        return kind, []
+    c = np.asarray(geom["c"], float).reshape(-1, dim)
+    m = np.asarray(geom["m"], float).reshape(-1, dim)
+    return kind, [float(geom["amp"]), float(len(c))] + list(c.reshape(-1)) + list(m.reshape(-1))
+
+
+def coefficient_params(coef: dict):
+    kind = COEF_KINDS[coef["kind"]]
+    if coef["kind"] == "one":
+        return kind, []
+    return kind, [coef["amp"], coef["f1"], coef["f2"], coef["phi1"], coef["phi2"]]
+
+
+class Context:
+    """Owner of an igafd_ctx handle; `handle` is passed to the igafd_* calls."""
+
+    def __init__(self, handle, n, N, nnz, band_bytes, dim):
+        self.handle = handle
+        self.n = n
+        self.N = N
+        self.nnz = nnz
+        self.band_bytes = band_bytes
+        self.dim = dim
+
+    @property
+    def shape(self):
+        return tuple(self.n[: self.dim][::-1])
+
+    def close(self):
+        if self.handle:
+            lib().igafd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def igafd_setup(problem: dict, stream=None) -> Context:
+    """Setup of one problem (host 1D setup + device assembly)."""
+    d = int(problem["dim"])
+    pr = igafd_problem()
+    pr.dim = d
+    pr.degree = int(problem["degree"])
+    keep = []
+    for l in range(3):
+        if l < d:
+            k = np.ascontiguousarray(problem["knots"][l], dtype=np.float64)
+            keep.append(k)
+            pr.nknots[l] = len(k)
+            pr.knots[l] = k.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            pr.nknots[l] = 0
+    gk, gp = geometry_params(problem["geometry"], d)
+    ck, cp = coefficient_params(problem["coefficient"])
+    gpa = (C.c_double * max(1, len(gp)))(*gp)
+    cpa = (C.c_double * max(1, len(cp)))(*cp)
+    pr.geom_kind, pr.n_geom_params, pr.geom_params = gk, len(gp), gpa
+    pr.coef_kind, pr.n_coef_params, pr.coef_params = ck, len(cp), cpa
+    pr.quad_per_dir = int(problem.get("quad", 0) or 0)
+    h = C.c_void_p()
+    _check(lib().igafd_setup(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
+    n, N, nnz, bb = igafd_sizes(h)
+    return Context(h, n, N, nnz, bb, d)
+
+
+def _h(ctx):
+    return ctx.handle if isinstance(ctx, Context) else ctx
+
+
+def igafd_sizes(ctx):
+    n = (C.c_int * 3)()
+    N, nnz, bb = C.c_longlong(), C.c_longlong(), C.c_longlong()
+    _check(lib().igafd_sizes(_h(ctx), n, C.byref(N), C.byref(nnz), C.byref(bb)))
+    return list(n), N.value, nnz.value, bb.value
+
+
+def igafd_load_vector(ctx: Context, rhs, b):
+    kind = RHS_KINDS[rhs["kind"]] if isinstance(rhs, dict) else int(rhs)
+    _check(lib().igafd_load_vector(_h(ctx), kind, _dptr(b, ctx.N, "b")))
+
+
+def igafd_apply_A(ctx: Context, x, y):
+    _check(lib().igafd_apply_A(_h(ctx), _dptr(x, ctx.N, "x"), _dptr(y, ctx.N, "y")))
+
+
+def igafd_apply_precond(ctx: Context, precision, r, s):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().igafd_apply_precond(_h(ctx), prec, _dptr(r, ctx.N, "r"), _dptr(s, ctx.N, "s")))
+
+
+def igafd_set_scaling(ctx: Context, S):
+    _check(lib().igafd_set_scaling(_h(ctx), None if S is None else _dptr(S, ctx.N, "S")))
+
+
+def igafd_diagonals(ctx: Context, dA=None, dP=None):
+    _check(lib().igafd_diagonals(_h(ctx), None if dA is None else _dptr(dA, ctx.N, "diagA"),
+                                 None if dP is None else _dptr(dP, ctx.N, "diagP")))
+
+
+def igafd_solve(ctx: Context, b, u, rtol=1e-8, maxit=2000, precision="fp64", flexible=None,
+                use_scaling=False, check_every=4, x0=False, history=False) -> dict:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if flexible is None:
+        flexible = prec != IGAFD_FP64
+    o = igafd_solve_opts()
+    o.rtol, o.maxit, o.precision, o.flexible = float(rtol), int(maxit), prec, int(bool(flexible))
+    o.use_scaling, o.check_every, o.use_x0 = int(bool(use_scaling)), int(check_every), int(bool(x0))
+    hist = None
+    if history:
+        hist = np.zeros(int(maxit) + 1)
+        o.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    info = igafd_solve_info()
+    st = _check(lib().igafd_solve(_h(ctx), _dptr(b, ctx.N, "b"), _dptr(u, ctx.N, "u"), C.byref(o), C.byref(info)))
+    out = {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
+           "true_relres": info.true_relres, "status": STATUS_NAMES.get(st, st), "t_solve_ms": info.t_solve_ms}
+    if hist is not None:
+        out["history"] = hist[: info.iters + 1].copy()
+    return out
+
+
+def igafd_get_eigen(ctx: Context, direction: int):
+    n = ctx.n[direction]
+    U = np.zeros((n, n))
+    lam = np.zeros(n)
+    _check(lib().igafd_get_eigen(_h(ctx), int(direction), U.ctypes.data_as(C.c_void_p),
+                                 lam.ctypes.data_as(C.c_void_p)))
+    return U, lam
+
+
+def igafd_univariate(degree: int, knots, quad: int = 0):
+    """Host-only 1D setup: (M, K, U, lam) for one knot vector."""
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    n = len(k) - degree - 3
+    if n < 1:
+        raise ValueError("no interior functions")
+    M, K, U = (np.zeros((n, n)) for _ in range(3))
+    lam = np.zeros(n)
+    nout = C.c_int()
+    _check(lib().igafd_univariate(int(degree), len(k), k.ctypes.data_as(C.POINTER(C.c_double)), int(quad),
+                                  M.ctypes.data_as(C.c_void_p), K.ctypes.data_as(C.c_void_p),
+                                  U.ctypes.data_as(C.c_void_p), lam.ctypes.data_as(C.c_void_p), C.byref(nout)))
+    return M, K, U, lam
+
+
+def igafd_destroy(ctx):
+    if isinstance(ctx, Context):
+        ctx.close()
+    elif ctx:
+        lib().igafd_destroy(ctx)

@@ -1,0 +1,642 @@
+// C ABI: setup, sizes, load vector, A product, preconditioner apply, PCG solve.
+//
+// The conjugate gradient method with the SPD preconditioner P (paper Sec. 3)
+// runs as a stream of device kernels whose scalars (rho, p^T A p, alpha,
+// beta, ||r||^2) live in device memory.  Every kernel of an iteration checks a
+// device stop flag first, so the host enqueues several iterations ahead and
+// reads the state back only every `check_every` iterations; iterations
+// enqueued past convergence are no-ops.  Reductions are per-block partial sums
+// finished by one block in a fixed order, so results are bitwise reproducible.
+//
+// Stopping rule (the paper states none): x0 = 0 unless given, stop when
+// ||r_k||_2 <= rtol ||b||_2 on the recursive residual; then the true residual
+// b - A x is evaluated in FP64 and the iteration restarts from it if it does
+// not meet the tolerance.  flexible = 1 uses the Polak-Ribiere beta
+// (r_{k+1}, z_{k+1} - z_k) / (r_k, z_k) for inexact (FP32/BF16) applies.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace igafd {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+enum { RED_BB_RR = 0, RED_PQ = 1, RED_RR = 2, RED_RZ = 3, RED_RHO0 = 4, RED_TRUE = 5 };
+
+// r = b - y (y = A x0, or r = b when y is null); x = 0 unless keep_x.
+// Partials: (b, b) and (r, r).
+__global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ b, const double* __restrict__ y,
+                                                 double* __restrict__ r, double* __restrict__ x, int keep_x,
+                                                 long long N, double* __restrict__ partial) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double bb = 0.0, rr = 0.0;
+  if (i < N) {
+    const double bi = b[i];
+    const double ri = y ? bi - y[i] : bi;
+    r[i] = ri;
+    if (!keep_x) x[i] = 0.0;
+    bb = bi * bi;
+    rr = ri * ri;
+  }
+  block_sum2(bb, rr);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = bb;
+    partial[gridDim.x + blockIdx.x] = rr;
+  }
+}
+
+// One block: sum partial[0..count) (and partial[count..2 count) when two
+// sums are pending) in a fixed order, then the scalar step of CG.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int count, int two, int which,
+                                                   SolverState* __restrict__ s, double* __restrict__ hist) {
+  if (which != RED_BB_RR && which != RED_RHO0 && which != RED_TRUE && s->flag != FLAG_RUNNING) return;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < count; k += kBlock) {
+    a += partial[k];
+    if (two) b += partial[count + k];
+  }
+  block_sum2(a, b);
+  if (threadIdx.x != 0) return;
+  switch (which) {
+    case RED_BB_RR:  // a = (b,b), b = (r,r)
+      s->bb = a;
+      s->tol2 = s->tol2 * a;  // tol2 holds rtol^2 on entry
+      s->rr = b;
+      s->iters = 0;
+      s->flag = (b <= s->tol2) ? FLAG_CONVERGED : FLAG_RUNNING;
+      if (hist) hist[0] = a > 0.0 ? sqrt(b / a) : 0.0;
+      break;
+    case RED_RHO0:
+      s->rho = a;
+      break;
+    case RED_PQ: {
+      s->pq = a;
+      if (!(a > 0.0) || !isfinite(a) || !isfinite(s->rho)) {
+        s->flag = FLAG_BREAKDOWN;
+      } else {
+        s->alpha = s->rho / a;
+        s->iters += 1;
+      }
+      break;
+    }
+    case RED_RR:  // a = (r,r), b = (r, z_old) for the flexible form
+      s->rr = a;
+      s->rzold = b;
+      if (hist) hist[s->iters] = s->bb > 0.0 ? sqrt(a / s->bb) : 0.0;
+      if (a <= s->tol2)
+        s->flag = FLAG_CONVERGED;
+      else if (!isfinite(a))
+        s->flag = FLAG_BREAKDOWN;
+      else if (s->iters >= s->maxit)
+        s->flag = FLAG_MAXIT;
+      break;
+    case RED_RZ: {
+      s->rz = a;
+      s->beta = s->flexible ? (a - s->rzold) / s->rho : a / s->rho;
+      s->rho = a;
+      break;
+    }
+    case RED_TRUE:
+      s->rrtrue = a;
+      break;
+  }
+}
+
+// x += alpha p; r -= alpha q; partials (r, r) and (r, z_old).
+__global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      const double* __restrict__ zold, const SolverState* __restrict__ s,
+                                                      long long N, double* __restrict__ partial) {
+  if (s->flag != FLAG_RUNNING) return;
+  const double alpha = s->alpha;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double rr = 0.0, rz = 0.0;
+  if (i < N) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    rr = ri * ri;
+    if (zold) rz = ri * zold[i];
+  }
+  block_sum2(rr, rz);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = rr;
+    partial[gridDim.x + blockIdx.x] = rz;
+  }
+}
+
+// p = z + beta p (beta = 0 on the first direction: p = z).
+__global__ __launch_bounds__(kBlock) void k_update_p(double* __restrict__ p, const double* __restrict__ z,
+                                                     const SolverState* __restrict__ s, int first, long long N) {
+  if (!first && s->flag != FLAG_RUNNING) return;
+  const double beta = first ? 0.0 : s->beta;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < N) p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+}
+
+// r = b - q and its squared norm (true residual).
+__global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ b, const double* __restrict__ q,
+                                                     double* __restrict__ r, long long N, double* __restrict__ partial) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double rr = 0.0;
+  if (i < N) {
+    const double ri = b[i] - q[i];
+    r[i] = ri;
+    rr = ri * ri;
+  }
+  const double t = block_sum(rr);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <typename T>
+igafd_status dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
+  IGAFD_HIP_CHECK(hipMalloc((void**)dst, sizeof(T) * (count ? count : 1)));
+  if (count) IGAFD_HIP_CHECK(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, st));
+  return IGAFD_OK;
+}
+
+uint16_t to_bf16_host(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Device copies of a direction: element tables, U^T and U in three
+// precisions (zero padded to npad x npad), eigenvalues, diagonals of M, K.
+igafd_status upload_dir(const Dir1D& h, DevDir* d, hipStream_t st) {
+  d->n = h.n;
+  d->nel = h.nel;
+  d->npad = fd_npad(h.n);
+  igafd_status s;
+  if ((s = dev_upload(&d->elem_first, h.elem_first.data(), h.elem_first.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->qx, h.qx.data(), h.qx.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->qw, h.qw.data(), h.qw.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->val, h.val.data(), h.val.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->der, h.der.data(), h.der.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->lam, h.lam.data(), h.lam.size(), st)) != IGAFD_OK) return s;
+  const int n = h.n, np = d->npad;
+  std::vector<double> w64((size_t)np * np);
+  std::vector<float> w32((size_t)np * np);
+  std::vector<uint16_t> wbf((size_t)np * np);
+  for (int which = 0; which < 2; ++which) {
+    std::fill(w64.begin(), w64.end(), 0.0);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) w64[(size_t)a * np + b] = which == 0 ? h.U[(size_t)b * n + a] : h.U[(size_t)a * n + b];
+    for (size_t k = 0; k < w64.size(); ++k) {
+      w32[k] = (float)w64[k];
+      wbf[k] = to_bf16_host((float)w64[k]);
+    }
+    if ((s = dev_upload(&d->W64[which], w64.data(), w64.size(), st)) != IGAFD_OK) return s;
+    if ((s = dev_upload(&d->W32[which], w32.data(), w32.size(), st)) != IGAFD_OK) return s;
+    if ((s = dev_upload(&d->Wbf[which], wbf.data(), wbf.size(), st)) != IGAFD_OK) return s;
+    IGAFD_HIP_CHECK(hipStreamSynchronize(st));  // host staging vectors are reused
+  }
+  std::vector<double> dm(n), dk(n);
+  for (int i = 0; i < n; ++i) {
+    dm[i] = h.M[(size_t)i * n + i];
+    dk[i] = h.K[(size_t)i * n + i];
+  }
+  if ((s = dev_upload(&d->diagM, dm.data(), dm.size(), st)) != IGAFD_OK) return s;
+  if ((s = dev_upload(&d->diagK, dk.data(), dk.size(), st)) != IGAFD_OK) return s;
+  // the host copies must outlive the asynchronous uploads
+  IGAFD_HIP_CHECK(hipStreamSynchronize(st));
+  return IGAFD_OK;
+}
+
+void free_dir(DevDir* d) {
+  free_dev(d->elem_first);
+  free_dev(d->qx);
+  free_dev(d->qw);
+  free_dev(d->val);
+  free_dev(d->der);
+  free_dev(d->lam);
+  for (int w = 0; w < 2; ++w) {
+    free_dev(d->W64[w]);
+    free_dev(d->W32[w]);
+    free_dev(d->Wbf[w]);
+  }
+  free_dev(d->diagM);
+  free_dev(d->diagK);
+  *d = DevDir{};
+}
+
+long long band_nnz(const igafd_ctx* c) {
+  long long nnz = 1;
+  for (int l = 0; l < c->dim; ++l) {
+    long long cnt = 0;
+    for (int i = 0; i < c->n[l]; ++i) {
+      const int lo = std::max(0, i - c->p), hi = std::min(c->n[l] - 1, i + c->p);
+      cnt += hi - lo + 1;
+    }
+    nnz *= cnt;
+  }
+  return nnz;
+}
+
+igafd_status parse_geometry(const igafd_problem* pr, GeomDesc* g) {
+  std::memset(g, 0, sizeof(*g));
+  g->dim = pr->dim;
+  g->kind = pr->geom_kind;
+  const double* gp = pr->geom_params;
+  switch (pr->geom_kind) {
+    case IGAFD_GEOM_IDENTITY:
+    case IGAFD_GEOM_RING:
+      break;
+    case IGAFD_GEOM_WARPED: {
+      if (!gp || pr->n_geom_params < 2) {
+        set_error("warped geometry needs [a, K, c..., m...]");
+        return IGAFD_ERR_ARG;
+      }
+      const int K = (int)gp[1];
+      if (K < 0 || K > kMaxModes || pr->n_geom_params != 2 + 2 * K * pr->dim) {
+        set_error("warped geometry: bad mode count or parameter length");
+        return IGAFD_ERR_ARG;
+      }
+      g->amp = gp[0];
+      g->nmodes = K;
+      for (int k = 0; k < K; ++k)
+        for (int l = 0; l < pr->dim; ++l) {
+          g->c[k][l] = gp[2 + k * pr->dim + l];
+          g->m[k][l] = gp[2 + K * pr->dim + k * pr->dim + l];
+        }
+      break;
+    }
+    default:
+      set_error("unknown geometry kind");
+      return IGAFD_ERR_ARG;
+  }
+  g->coef_kind = pr->coef_kind;
+  switch (pr->coef_kind) {
+    case IGAFD_COEF_ONE:
+      break;
+    case IGAFD_COEF_SINCOS:
+      if (!pr->coef_params || pr->n_coef_params != 5) {
+        set_error("sincos coefficient needs [a, f1, f2, phi1, phi2]");
+        return IGAFD_ERR_ARG;
+      }
+      g->camp = pr->coef_params[0];
+      g->f1 = pr->coef_params[1];
+      g->f2 = pr->coef_params[2];
+      g->phi1 = pr->coef_params[3];
+      g->phi2 = pr->coef_params[4];
+      break;
+    default:
+      set_error("unknown coefficient kind");
+      return IGAFD_ERR_ARG;
+  }
+  return IGAFD_OK;
+}
+
+igafd_status alloc_workspace(igafd_ctx* c) {
+  const size_t vb = sizeof(double) * (size_t)c->N;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->r, vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->z, vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->zold, vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->pv, vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->q, vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[0], vb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[1], vb));
+  c->npartial = std::max(spmv_blocks(c), fd_dot_blocks(c));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->state, sizeof(SolverState)));
+  IGAFD_HIP_CHECK(hipHostMalloc((void**)&c->hstate, sizeof(SolverState), hipHostMallocDefault));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->dflag, sizeof(int)));
+  IGAFD_HIP_CHECK(hipEventCreate(&c->ev0));
+  IGAFD_HIP_CHECK(hipEventCreate(&c->ev1));
+  return IGAFD_OK;
+}
+
+unsigned vblocks(const igafd_ctx* c) { return (unsigned)((c->N + kBlock - 1) / kBlock); }
+
+igafd_status reduce(igafd_ctx* c, int count, int two, int which, double* hist) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, c->stream, c->partial, count, two, which, c->state, hist);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+igafd_status read_state(igafd_ctx* c) {
+  IGAFD_HIP_CHECK(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return IGAFD_OK;
+}
+
+#define IGAFD_TRY(x)                          \
+  do {                                        \
+    igafd_status st_ = (x);                   \
+    if (st_ != IGAFD_OK) return st_;          \
+  } while (0)
+
+// z = M r with M = P^-1 or S P^-1 S; (r, z) partials; then rho or beta.
+igafd_status precond_step(igafd_ctx* c, int prec, const double* S, double* z, int which, const int* flag) {
+  IGAFD_TRY(fd_apply(c, prec, c->r, z, S, c->partial, flag));
+  return reduce(c, fd_dot_blocks(c), 0, which, nullptr);
+}
+
+// (Re)start: r holds the residual; z = M r, rho = (r, z), p = z.
+igafd_status start_directions(igafd_ctx* c, int prec, const double* S, double*& z, double*& zold) {
+  IGAFD_TRY(fd_apply(c, prec, c->r, z, S, c->partial, nullptr));
+  IGAFD_TRY(reduce(c, fd_dot_blocks(c), 0, RED_RHO0, nullptr));
+  hipLaunchKernelGGL(k_update_p, dim3(vblocks(c)), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 1, c->N);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  (void)zold;
+  return IGAFD_OK;
+}
+
+igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_solve_opts* o, igafd_solve_info* info) {
+  const int maxit = o->maxit > 0 ? o->maxit : 2000;
+  const int chunk = o->check_every > 0 ? o->check_every : 4;
+  const int prec = o->precision;
+  const int flexible = o->flexible ? 1 : 0;
+  if (prec != IGAFD_FP64 && !flexible) {
+    set_error("FP32/BF16 preconditioner applies need the flexible CG form");
+    return IGAFD_ERR_ARG;
+  }
+  if (!(o->rtol > 0.0)) {
+    set_error("rtol must be positive");
+    return IGAFD_ERR_ARG;
+  }
+  const double* S = nullptr;
+  if (o->use_scaling) {
+    if (!c->scaling_set) {
+      set_error("use_scaling requested but no scaling set");
+      return IGAFD_ERR_ARG;
+    }
+    S = c->scaling;
+  }
+  double* hist = nullptr;
+  if (o->history) IGAFD_HIP_CHECK(hipMalloc((void**)&hist, sizeof(double) * (maxit + 1)));
+  const unsigned vb = vblocks(c);
+  const int* flag = &c->state->flag;
+  IGAFD_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
+
+  SolverState init{};
+  init.tol2 = o->rtol * o->rtol;
+  init.maxit = maxit;
+  init.flexible = flexible;
+  *c->hstate = init;
+  IGAFD_HIP_CHECK(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
+  const double* y = nullptr;
+  if (o->use_x0) {
+    IGAFD_TRY(spmv(c, x, c->q, nullptr, nullptr));
+    y = c->q;
+  }
+  hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, b, y, c->r, x, o->use_x0 ? 1 : 0, c->N, c->partial);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  IGAFD_TRY(reduce(c, (int)vb, 1, RED_BB_RR, hist));
+  IGAFD_TRY(read_state(c));
+  const double bb = c->hstate->bb;
+
+  double* z = c->z;
+  double* zold = c->zold;
+  int restarts = 0;
+  double true_rel = 0.0;
+  int status = IGAFD_OK;
+  while (true) {
+    if (c->hstate->flag == FLAG_RUNNING) {
+      IGAFD_TRY(start_directions(c, prec, S, z, zold));
+      while (true) {
+        for (int k = 0; k < chunk; ++k) {
+          // q = A p, (p, q)
+          IGAFD_TRY(spmv(c, c->pv, c->q, c->partial, flag));
+          IGAFD_TRY(reduce(c, spmv_blocks(c), 0, RED_PQ, hist));
+          // x += alpha p, r -= alpha q, (r, r) [, (r, z_old)]
+          hipLaunchKernelGGL(k_update_xr, dim3(vb), dim3(kBlock), 0, c->stream, x, c->r, c->pv, c->q,
+                             flexible ? z : nullptr, c->state, c->N, c->partial);
+          IGAFD_HIP_CHECK(hipGetLastError());
+          IGAFD_TRY(reduce(c, (int)vb, flexible, RED_RR, hist));
+          // z = M r, (r, z) -> beta; the previous z stays as z_old for the flexible form
+          std::swap(z, zold);
+          IGAFD_TRY(precond_step(c, prec, S, z, RED_RZ, flag));
+          hipLaunchKernelGGL(k_update_p, dim3(vb), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 0, c->N);
+          IGAFD_HIP_CHECK(hipGetLastError());
+        }
+        IGAFD_TRY(read_state(c));
+        if (c->hstate->flag != FLAG_RUNNING) break;
+      }
+    }
+    // true residual in FP64
+    IGAFD_TRY(spmv(c, x, c->q, nullptr, nullptr));
+    hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, b, c->q, c->r, c->N, c->partial);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    IGAFD_TRY(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
+    IGAFD_TRY(read_state(c));
+    const SolverState hs = *c->hstate;
+    true_rel = bb > 0.0 ? std::sqrt(hs.rrtrue / bb) : 0.0;
+    if (hs.flag == FLAG_BREAKDOWN) {
+      status = IGAFD_ERR_BREAKDOWN;
+      break;
+    }
+    if (true_rel <= o->rtol) {
+      status = IGAFD_OK;
+      break;
+    }
+    if (hs.iters >= maxit || restarts >= 3) {
+      status = IGAFD_NOT_CONVERGED;
+      break;
+    }
+    // restart from the true residual (held in r)
+    ++restarts;
+    c->hstate->flag = FLAG_RUNNING;
+    IGAFD_HIP_CHECK(hipMemcpyAsync(&c->state->flag, &c->hstate->flag, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  }
+  IGAFD_HIP_CHECK(hipEventRecord(c->ev1, c->stream));
+  IGAFD_TRY(read_state(c));
+  const SolverState hs = *c->hstate;
+  float ms = 0.f;
+  IGAFD_HIP_CHECK(hipEventSynchronize(c->ev1));
+  IGAFD_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (hist) {
+    const int nh = std::min(hs.iters, maxit) + 1;
+    IGAFD_HIP_CHECK(hipMemcpyAsync(o->history, hist, sizeof(double) * nh, hipMemcpyDeviceToHost, c->stream));
+    IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+    IGAFD_HIP_CHECK(hipFree(hist));
+  }
+  if (info) {
+    info->iters = hs.iters;
+    info->restarts = restarts;
+    info->true_relres = true_rel;
+    info->status = status;
+    info->t_solve_ms = ms;
+    info->relres = bb > 0.0 ? std::sqrt(hs.rr / bb) : 0.0;
+  }
+  if (status == IGAFD_ERR_BREAKDOWN) set_error("CG breakdown: p^T A p <= 0 or not finite");
+  return (igafd_status)status;
+}
+
+}  // namespace
+}  // namespace igafd
+
+using namespace igafd;
+
+extern "C" {
+
+const char* igafd_last_error(void) { return g_err.c_str(); }
+
+igafd_status igafd_univariate(int degree, int nknots, const double* knots, int quad, double* M, double* K, double* U,
+                              double* lam, int* n_out) {
+  Dir1D d;
+  const int q = quad > 0 ? quad : degree + 1;
+  igafd_status s = build_direction(degree, q, nknots, knots, &d);
+  if (s != IGAFD_OK) return s;
+  if (n_out) *n_out = d.n;
+  if (M) std::memcpy(M, d.M.data(), sizeof(double) * d.M.size());
+  if (K) std::memcpy(K, d.K.data(), sizeof(double) * d.K.size());
+  if (U) std::memcpy(U, d.U.data(), sizeof(double) * d.U.size());
+  if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * d.lam.size());
+  return IGAFD_OK;
+}
+
+void igafd_destroy(igafd_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int l = 0; l < 3; ++l) free_dir(&c->ddir[l]);
+  free_dev(c->band);
+  free_dev(c->r);
+  free_dev(c->z);
+  free_dev(c->zold);
+  free_dev(c->pv);
+  free_dev(c->q);
+  free_dev(c->fdbuf[0]);
+  free_dev(c->fdbuf[1]);
+  free_dev(c->scaling);
+  free_dev(c->partial);
+  free_dev(c->state);
+  free_dev(c->dflag);
+  if (c->hstate) (void)hipHostFree(c->hstate);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out) {
+  if (!pr || !out) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  *out = nullptr;
+  if (pr->dim != 2 && pr->dim != 3) {
+    set_error("dim must be 2 or 3");
+    return IGAFD_ERR_ARG;
+  }
+  std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(new igafd_ctx(), igafd_destroy);
+  c->dim = pr->dim;
+  c->p = pr->degree;
+  c->stream = (hipStream_t)stream;
+  const int q = pr->quad_per_dir > 0 ? pr->quad_per_dir : pr->degree + 1;
+  igafd_status s;
+  if ((s = parse_geometry(pr, &c->geom)) != IGAFD_OK) return s;
+  c->N = 1;
+  for (int l = 0; l < pr->dim; ++l) {
+    if ((s = build_direction(pr->degree, q, pr->nknots[l], pr->knots[l], &c->dir[l])) != IGAFD_OK) return s;
+    c->n[l] = c->dir[l].n;
+    c->N *= c->n[l];
+  }
+  for (int l = 0; l < pr->dim; ++l)
+    if ((s = upload_dir(c->dir[l], &c->ddir[l], c->stream)) != IGAFD_OK) return s;
+  const int W = 2 * c->p + 1;
+  const int Sz = (c->dim == 3) ? W * W * W : W * W;
+  c->H = (Sz + 1) / 2;
+  c->Np = (c->N + 63) / 64 * 64;
+  c->nnz = band_nnz(c.get());
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Np));
+  if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
+  if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  *out = c.release();
+  return IGAFD_OK;
+}
+
+igafd_status igafd_sizes(const igafd_ctx* c, int n[3], long long* N, long long* nnz, long long* band_bytes) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (n)
+    for (int l = 0; l < 3; ++l) n[l] = c->n[l];
+  if (N) *N = c->N;
+  if (nnz) *nnz = c->nnz;
+  if (band_bytes) *band_bytes = (long long)sizeof(double) * c->H * c->Np;
+  return IGAFD_OK;
+}
+
+igafd_status igafd_load_vector(igafd_ctx* c, int rhs_kind, double* b) {
+  if (!c || !b) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  return assemble_load(c, rhs_kind, b);
+}
+
+igafd_status igafd_apply_A(igafd_ctx* c, const double* x, double* y) {
+  if (!c || !x || !y || x == y) {
+    set_error("apply_A needs distinct non-null vectors");
+    return IGAFD_ERR_ARG;
+  }
+  return spmv(c, x, y, nullptr, nullptr);
+}
+
+igafd_status igafd_apply_precond(igafd_ctx* c, int precision, const double* r, double* s) {
+  if (!c || !r || !s || r == s) {
+    set_error("apply_precond needs distinct non-null vectors");
+    return IGAFD_ERR_ARG;
+  }
+  return fd_apply(c, precision, r, s, c->scaling_set ? c->scaling : nullptr, nullptr, nullptr);
+}
+
+igafd_status igafd_set_scaling(igafd_ctx* c, const double* S) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (!S) {
+    c->scaling_set = false;
+    return IGAFD_OK;
+  }
+  if (!c->scaling) IGAFD_HIP_CHECK(hipMalloc((void**)&c->scaling, sizeof(double) * c->N));
+  IGAFD_HIP_CHECK(hipMemcpyAsync(c->scaling, S, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+  c->scaling_set = true;
+  return IGAFD_OK;
+}
+
+igafd_status igafd_diagonals(igafd_ctx* c, double* dA, double* dP) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  return diagonals(c, dA, dP);
+}
+
+igafd_status igafd_get_eigen(const igafd_ctx* c, int dir, double* U, double* lam) {
+  if (!c || dir < 0 || dir >= c->dim) {
+    set_error("bad context or direction");
+    return IGAFD_ERR_ARG;
+  }
+  const Dir1D& d = c->dir[dir];
+  if (U) std::memcpy(U, d.U.data(), sizeof(double) * d.U.size());
+  if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * d.lam.size());
+  return IGAFD_OK;
+}
+
+igafd_status igafd_solve(igafd_ctx* c, const double* b, double* u, const igafd_solve_opts* o, igafd_solve_info* info) {
+  if (!c || !b || !u || !o || b == u) {
+    set_error("solve needs a context, distinct b and u, and options");
+    return IGAFD_ERR_ARG;
+  }
+  return solve_impl(c, b, u, o, info);
+}
+
+}  // extern "C"

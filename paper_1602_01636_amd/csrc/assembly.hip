@@ -1,0 +1,444 @@
+// Device assembly of the Galerkin stiffness matrix A and of the load vector b.
+//
+// Paper Sec. 2.1 eq. A / eq. Q: A_ij = int_[0,1]^d grad(B_i)^T Q grad(B_j) with
+// Q = |det J| J^-1 K J^-T (J_ij = dF_i/dxi_j), by the tensor (p+1)-point Gauss
+// rule on every element.  One workgroup per element:
+//   1. geometry at the element's (p+1)^d Gauss points -> C = w Q in LDS
+//      (Q = kappa adj(J) adj(J)^T / |det J|, computed without an inverse),
+//   2. local matrix by sum factorisation over the tensor Gauss rule: for a
+//      fixed pair of direction-3 functions, contract the t3 points, then the t2
+//      points, then the t1 points (the same sum, reordered),
+//   3. add into the symmetric band.  Elements are processed in (p+1)^d colour
+//      classes (element index mod p+1 per direction): two elements of one class
+//      share no basis function, so the += needs no atomics and the summation
+//      order is fixed (bitwise reproducible).
+// Only the upper half of the stencil is stored: plane h holds offset
+// center + h of the (2p+1)^d stencil, indexed by the row.
+#include "internal.h"
+
+namespace igafd {
+namespace {
+
+struct Tables {
+  const int* first[3];
+  const double* qx[3];
+  const double* qw[3];
+  const double* val[3];
+  const double* der[3];
+  int n[3];
+};
+
+template <int D>
+__device__ inline void map_eval(const GeomDesc& g, const double xi[3], double x[3], double J[3][3]) {
+  for (int a = 0; a < 3; ++a) {
+    x[a] = xi[a];
+    for (int b = 0; b < 3; ++b) J[a][b] = (a == b) ? 1.0 : 0.0;
+  }
+  if (g.kind == IGAFD_GEOM_RING) {
+    const double r = 1.0 + xi[0];
+    const double th = 0.5 * M_PI * xi[1];
+    double s, c;
+    sincos(th, &s, &c);
+    x[0] = r * c;
+    x[1] = r * s;
+    J[0][0] = c;
+    J[0][1] = -0.5 * M_PI * r * s;
+    J[1][0] = s;
+    J[1][1] = 0.5 * M_PI * r * c;
+  } else if (g.kind == IGAFD_GEOM_WARPED) {
+    for (int k = 0; k < g.nmodes; ++k) {
+      double sn[3], dc[3];
+      for (int l = 0; l < D; ++l) {
+        double s, c;
+        sincos(M_PI * g.m[k][l] * xi[l], &s, &c);
+        sn[l] = s;
+        dc[l] = M_PI * g.m[k][l] * c;
+      }
+      double prod = 1.0;
+      for (int l = 0; l < D; ++l) prod *= sn[l];
+      for (int a = 0; a < D; ++a) x[a] += g.amp * g.c[k][a] * prod;
+      for (int j = 0; j < D; ++j) {
+        double others = dc[j];
+        for (int l = 0; l < D; ++l)
+          if (l != j) others *= sn[l];
+        for (int a = 0; a < D; ++a) J[a][j] += g.amp * g.c[k][a] * others;
+      }
+    }
+  }
+}
+
+__device__ inline double kappa_eval(const GeomDesc& g, const double x[3]) {
+  if (g.coef_kind == IGAFD_COEF_SINCOS)
+    return 1.0 + g.camp * sin(2.0 * M_PI * g.f1 * x[0] + g.phi1) * cos(2.0 * M_PI * g.f2 * x[1] + g.phi2);
+  return 1.0;
+}
+
+// det J and the cofactor matrix adj(J) (so that J^-1 = adj / det).
+template <int D>
+__device__ inline double adjugate(const double J[3][3], double A[3][3]) {
+  if (D == 2) {
+    A[0][0] = J[1][1];
+    A[0][1] = -J[0][1];
+    A[1][0] = -J[1][0];
+    A[1][1] = J[0][0];
+    return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  }
+  A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  return J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+}
+
+template <int D>
+__host__ __device__ constexpr int sym_index(int a, int b) {
+  return (a == b) ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, double* __restrict__ band,
+                                                     long long Np, int c1, int c2, int c3, int m1, int m2,
+                                                     int* __restrict__ err) {
+  constexpr int Q = P + 1, L = P + 1;
+  constexpr int Q3 = (D == 3) ? Q : 1;
+  constexpr int L3 = (D == 3) ? L : 1;
+  constexpr int NQ = Q * Q * Q3;
+  constexpr int NC = (D == 3) ? 6 : 3;
+  constexpr int NAB = D * D;
+  constexpr int W = 2 * P + 1;
+  constexpr int S = (D == 3) ? W * W * W : W * W;
+  constexpr int CENTER = (S - 1) / 2;
+  constexpr int R3 = (D == 3) ? P : 0;
+
+  __shared__ double sC[NC][NQ];
+  __shared__ double sV[3][Q][L];
+  __shared__ double sD[3][Q][L];
+  __shared__ double sH[NAB][Q * Q];
+  __shared__ double sG[NAB][L * L][Q];
+  __shared__ int sFirst[3];
+
+  int bid = blockIdx.x;
+  const int j1 = bid % m1;
+  bid /= m1;
+  const int j2 = bid % m2;
+  const int j3 = bid / m2;
+  const int e[3] = {c1 + j1 * (P + 1), c2 + j2 * (P + 1), (D == 3) ? c3 + j3 * (P + 1) : 0};
+  const int tid = threadIdx.x;
+
+  for (int idx = tid; idx < 3 * Q * L; idx += kBlock) {
+    const int l = idx / (Q * L), t = (idx / L) % Q, a = idx % L;
+    if (l < D) {
+      sV[l][t][a] = T.val[l][(e[l] * Q + t) * L + a];
+      sD[l][t][a] = T.der[l][(e[l] * Q + t) * L + a];
+    } else {
+      sV[l][t][a] = (t == 0 && a == 0) ? 1.0 : 0.0;
+      sD[l][t][a] = 0.0;
+    }
+  }
+  if (tid < 3) sFirst[tid] = (tid < D) ? T.first[tid][e[tid]] : 1;
+
+  for (int t = tid; t < NQ; t += kBlock) {
+    const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
+    double xi[3] = {T.qx[0][e[0] * Q + t1], T.qx[1][e[1] * Q + t2], 0.0};
+    double w = T.qw[0][e[0] * Q + t1] * T.qw[1][e[1] * Q + t2];
+    if (D == 3) {
+      xi[2] = T.qx[2][e[2] * Q + t3];
+      w *= T.qw[2][e[2] * Q + t3];
+    }
+    double x[3], J[3][3], A[3][3];
+    map_eval<D>(g, xi, x, J);
+    const double det = adjugate<D>(J, A);
+    if (!(det > 0.0)) *err = 1;
+    const double f = w * kappa_eval(g, x) / fabs(det);
+    for (int a = 0; a < D; ++a)
+      for (int b = a; b < D; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s += A[a][k] * A[b][k];
+        sC[sym_index<D>(a, b)][t] = f * s;
+      }
+  }
+  __syncthreads();
+
+  for (int a3 = 0; a3 < L3; ++a3) {
+    for (int b3 = a3; b3 < L3; ++b3) {
+      // H[ab][t1 + Q t2] = sum_t3 C_ab(t) phi3(a3) phi3(b3)
+      for (int idx = tid; idx < NAB * Q * Q; idx += kBlock) {
+        const int ab = idx / (Q * Q), t12 = idx % (Q * Q);
+        const int a = ab / D, b = ab % D;
+        const int ci = sym_index<D>(a, b);
+        double s = 0.0;
+#pragma unroll
+        for (int t3 = 0; t3 < Q3; ++t3) {
+          const double fa = (a == 2) ? sD[2][t3][a3] : sV[2][t3][a3];
+          const double fb = (b == 2) ? sD[2][t3][b3] : sV[2][t3][b3];
+          s += sC[ci][t12 + Q * Q * t3] * fa * fb;
+        }
+        sH[ab][t12] = s;
+      }
+      __syncthreads();
+      // G[ab][a2 + L b2][t1] = sum_t2 H[ab][t1 + Q t2] phi2(a2) phi2(b2)
+      for (int idx = tid; idx < NAB * L * L * Q; idx += kBlock) {
+        const int ab = idx / (L * L * Q), rem = idx % (L * L * Q);
+        const int a2b2 = rem / Q, t1 = rem % Q;
+        const int a2 = a2b2 % L, b2 = a2b2 / L;
+        const int a = ab / D, b = ab % D;
+        double s = 0.0;
+#pragma unroll
+        for (int t2 = 0; t2 < Q; ++t2) {
+          const double fa = (a == 1) ? sD[1][t2][a2] : sV[1][t2][a2];
+          const double fb = (b == 1) ? sD[1][t2][b2] : sV[1][t2][b2];
+          s += sH[ab][t1 + Q * t2] * fa * fb;
+        }
+        sG[ab][a2b2][t1] = s;
+      }
+      __syncthreads();
+      // local entry (a1 a2 a3 | b1 b2 b3) = sum_ab sum_t1 G phi1(a1) phi1(b1)
+      for (int idx = tid; idx < L * L * L * L; idx += kBlock) {
+        const int a1 = idx % L, b1 = (idx / L) % L, a2 = (idx / (L * L)) % L, b2 = idx / (L * L * L);
+        const int o1 = b1 - a1, o2 = b2 - a2, o3 = b3 - a3;
+        if (o3 == 0 && (o2 < 0 || (o2 == 0 && o1 < 0))) continue;  // lower half: not stored
+        const int r1 = sFirst[0] + a1 - 1, r2 = sFirst[1] + a2 - 1, r3 = (D == 3) ? sFirst[2] + a3 - 1 : 0;
+        const int q1 = r1 + o1, q2 = r2 + o2, q3 = r3 + o3;
+        if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
+        if (q1 < 0 || q1 >= T.n[0] || q2 < 0 || q2 >= T.n[1] || q3 < 0 || q3 >= T.n[2]) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) {
+          const int a = ab / D, b = ab % D;
+#pragma unroll
+          for (int t1 = 0; t1 < Q; ++t1) {
+            const double fa = (a == 0) ? sD[0][t1][a1] : sV[0][t1][a1];
+            const double fb = (b == 0) ? sD[0][t1][b1] : sV[0][t1][b1];
+            s += sG[ab][a2 + L * b2][t1] * fa * fb;
+          }
+        }
+        const int oidx = ((o3 + R3) * W + (o2 + P)) * W + (o1 + P);
+        const long long row = r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3);
+        band[(long long)(oidx - CENTER) * Np + row] += s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int D>
+__device__ inline double rhs_eval(int kind, const double x[3]) {
+  switch (kind) {
+    case IGAFD_RHS_SINPROD: {
+      double s = D * M_PI * M_PI;
+      for (int l = 0; l < D; ++l) s *= sin(M_PI * x[l]);
+      return s;
+    }
+    case IGAFD_RHS_PAPER_POLY: {
+      double s = 0.0;
+      for (int l = 0; l < D; ++l) s += 2.0 * (x[l] * x[l] - x[l]);
+      return s;
+    }
+    case IGAFD_RHS_BUBBLE: {
+      double s = 0.0;
+      for (int i = 0; i < D; ++i) {
+        double pr = 2.0;
+        for (int l = 0; l < D; ++l)
+          if (l != i) pr *= x[l] * (1.0 - x[l]);
+        s += pr;
+      }
+      return s;
+    }
+    default:
+      return 1.0;
+  }
+}
+
+// b_i += sum_t w_t |det J| f(F(t)) B_i(t) over one colour class of elements.
+template <int D, int P>
+__global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, int rhs_kind, double* __restrict__ b,
+                                                 int c1, int c2, int c3, int m1, int m2) {
+  constexpr int Q = P + 1, L = P + 1;
+  constexpr int Q3 = (D == 3) ? Q : 1;
+  constexpr int L3 = (D == 3) ? L : 1;
+  constexpr int NQ = Q * Q * Q3;
+  __shared__ double sg[NQ];
+  __shared__ double sV[3][Q][L];
+  int bid = blockIdx.x;
+  const int j1 = bid % m1;
+  bid /= m1;
+  const int j2 = bid % m2;
+  const int j3 = bid / m2;
+  const int e[3] = {c1 + j1 * (P + 1), c2 + j2 * (P + 1), (D == 3) ? c3 + j3 * (P + 1) : 0};
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 3 * Q * L; idx += kBlock) {
+    const int l = idx / (Q * L), t = (idx / L) % Q, a = idx % L;
+    sV[l][t][a] = (l < D) ? T.val[l][(e[l] * Q + t) * L + a] : ((t == 0 && a == 0) ? 1.0 : 0.0);
+  }
+  for (int t = tid; t < NQ; t += kBlock) {
+    const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
+    double xi[3] = {T.qx[0][e[0] * Q + t1], T.qx[1][e[1] * Q + t2], 0.0};
+    double w = T.qw[0][e[0] * Q + t1] * T.qw[1][e[1] * Q + t2];
+    if (D == 3) {
+      xi[2] = T.qx[2][e[2] * Q + t3];
+      w *= T.qw[2][e[2] * Q + t3];
+    }
+    double x[3], J[3][3], A[3][3];
+    map_eval<D>(g, xi, x, J);
+    const double det = adjugate<D>(J, A);
+    sg[t] = w * fabs(det) * rhs_eval<D>(rhs_kind, x);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < L * L * L3; idx += kBlock) {
+    const int a1 = idx % L, a2 = (idx / L) % L, a3 = idx / (L * L);
+    const int r1 = T.first[0][e[0]] + a1 - 1, r2 = T.first[1][e[1]] + a2 - 1;
+    const int r3 = (D == 3) ? T.first[2][e[2]] + a3 - 1 : 0;
+    if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
+    double s = 0.0;
+    for (int t = 0; t < NQ; ++t) {
+      const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
+      s += sg[t] * sV[0][t1][a1] * sV[1][t2][a2] * sV[2][t3][a3];
+    }
+    b[r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)] += s;
+  }
+}
+
+// diag(P) = sum_j K_j[i_j, i_j] prod_{l != j} M_l[i_l, i_l]  (Sec. 3 Kronecker sum)
+__global__ void k_diagP(const double* m1, const double* k1, const double* m2, const double* k2,
+                        const double* m3, const double* k3, int n1, int n2, long long N, int dim,
+                        double* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int i1 = (int)(i % n1);
+  const long long t = i / n1;
+  const int i2 = (int)(t % n2), i3 = (int)(t / n2);
+  if (dim == 2)
+    out[i] = k1[i1] * m2[i2] + m1[i1] * k2[i2];
+  else
+    out[i] = k1[i1] * m2[i2] * m3[i3] + m1[i1] * k2[i2] * m3[i3] + m1[i1] * m2[i2] * k3[i3];
+}
+
+__global__ void k_copy_plane(const double* __restrict__ src, double* __restrict__ dst, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[i];
+}
+
+Tables make_tables(const igafd_ctx* c) {
+  Tables T{};
+  for (int l = 0; l < 3; ++l) {
+    T.first[l] = c->ddir[l].elem_first;
+    T.qx[l] = c->ddir[l].qx;
+    T.qw[l] = c->ddir[l].qw;
+    T.val[l] = c->ddir[l].val;
+    T.der[l] = c->ddir[l].der;
+    T.n[l] = c->n[l];
+  }
+  return T;
+}
+
+template <int D, int P>
+igafd_status launch_assemble(igafd_ctx* c) {
+  const Tables T = make_tables(c);
+  const int nel[3] = {c->ddir[0].nel, c->ddir[1].nel, D == 3 ? c->ddir[2].nel : 1};
+  const int C3 = (D == 3) ? P + 1 : 1;
+  for (int c3 = 0; c3 < C3; ++c3)
+    for (int c2 = 0; c2 <= P; ++c2)
+      for (int c1 = 0; c1 <= P; ++c1) {
+        const int m1 = c1 < nel[0] ? (nel[0] - c1 + P) / (P + 1) : 0;
+        const int m2 = c2 < nel[1] ? (nel[1] - c2 + P) / (P + 1) : 0;
+        const int m3 = (D == 3) ? (c3 < nel[2] ? (nel[2] - c3 + P) / (P + 1) : 0) : 1;
+        const long long blocks = (long long)m1 * m2 * m3;
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL((k_assemble<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom,
+                           c->band, c->Np, c1, c2, c3, m1, m2, c->dflag);
+        IGAFD_HIP_CHECK(hipGetLastError());
+      }
+  return IGAFD_OK;
+}
+
+template <int D, int P>
+igafd_status launch_load(igafd_ctx* c, int rhs_kind, double* b) {
+  const Tables T = make_tables(c);
+  const int nel[3] = {c->ddir[0].nel, c->ddir[1].nel, D == 3 ? c->ddir[2].nel : 1};
+  const int C3 = (D == 3) ? P + 1 : 1;
+  for (int c3 = 0; c3 < C3; ++c3)
+    for (int c2 = 0; c2 <= P; ++c2)
+      for (int c1 = 0; c1 <= P; ++c1) {
+        const int m1 = c1 < nel[0] ? (nel[0] - c1 + P) / (P + 1) : 0;
+        const int m2 = c2 < nel[1] ? (nel[1] - c2 + P) / (P + 1) : 0;
+        const int m3 = (D == 3) ? (c3 < nel[2] ? (nel[2] - c3 + P) / (P + 1) : 0) : 1;
+        const long long blocks = (long long)m1 * m2 * m3;
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL((k_load<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom, rhs_kind,
+                           b, c1, c2, c3, m1, m2);
+        IGAFD_HIP_CHECK(hipGetLastError());
+      }
+  return IGAFD_OK;
+}
+
+template <template <int, int> class F, typename... Args>
+igafd_status dispatch(int dim, int p, Args... args) {
+  switch (dim * 10 + p) {
+#define IGAFD_CASE(D, P) \
+  case D * 10 + P:       \
+    return F<D, P>::run(args...);
+    IGAFD_CASE(2, 1) IGAFD_CASE(2, 2) IGAFD_CASE(2, 3) IGAFD_CASE(2, 4) IGAFD_CASE(2, 5) IGAFD_CASE(2, 6)
+    IGAFD_CASE(3, 1) IGAFD_CASE(3, 2) IGAFD_CASE(3, 3) IGAFD_CASE(3, 4) IGAFD_CASE(3, 5) IGAFD_CASE(3, 6)
+#undef IGAFD_CASE
+    default:
+      set_error("unsupported dimension/degree");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+template <int D, int P>
+struct AssembleOp {
+  static igafd_status run(igafd_ctx* c) { return launch_assemble<D, P>(c); }
+};
+template <int D, int P>
+struct LoadOp {
+  static igafd_status run(igafd_ctx* c, int k, double* b) { return launch_load<D, P>(c, k, b); }
+};
+
+}  // namespace
+
+igafd_status assemble_band(igafd_ctx* c) {
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->band, 0, sizeof(double) * c->H * c->Np, c->stream));
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+  igafd_status st = dispatch<AssembleOp>(c->dim, c->p, c);
+  if (st != IGAFD_OK) return st;
+  int flag = 0;
+  IGAFD_HIP_CHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  if (flag) {
+    set_error("det J <= 0 at a quadrature point");
+    return IGAFD_ERR_GEOMETRY;
+  }
+  return IGAFD_OK;
+}
+
+igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b) {
+  if (rhs_kind < IGAFD_RHS_SINPROD || rhs_kind > IGAFD_RHS_ONE) {
+    set_error("unknown right-hand side kind");
+    return IGAFD_ERR_ARG;
+  }
+  IGAFD_HIP_CHECK(hipMemsetAsync(b, 0, sizeof(double) * c->N, c->stream));
+  return dispatch<LoadOp>(c->dim, c->p, c, rhs_kind, b);
+}
+
+igafd_status diagonals(igafd_ctx* c, double* dA, double* dP) {
+  const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+  if (dA) {  // plane 0 of the band is the diagonal
+    hipLaunchKernelGGL(k_copy_plane, dim3(blocks), dim3(kBlock), 0, c->stream, c->band, dA, c->N);
+    IGAFD_HIP_CHECK(hipGetLastError());
+  }
+  if (dP) {
+    const DevDir* d = c->ddir;
+    hipLaunchKernelGGL(k_diagP, dim3(blocks), dim3(kBlock), 0, c->stream, d[0].diagM, d[0].diagK, d[1].diagM,
+                       d[1].diagK, d[2].diagM, d[2].diagK, c->n[0], c->n[1], c->N, c->dim, dP);
+    IGAFD_HIP_CHECK(hipGetLastError());
+  }
+  return IGAFD_OK;
+}
+
+}  // namespace igafd

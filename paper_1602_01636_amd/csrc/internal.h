@@ -1,0 +1,121 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "igafd.h"
+
+namespace igafd {
+
+constexpr int kMaxDegree = 6;
+constexpr int kMaxModes = 16;
+constexpr int kBlock = 256;
+
+void set_error(const std::string& msg);
+
+#define IGAFD_HIP_CHECK(expr)                                                        \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::igafd::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return IGAFD_ERR_HIP;                                                         \
+    }                                                                               \
+  } while (0)
+
+// Geometry map and coefficient, passed by value to the device.
+struct GeomDesc {
+  int dim;
+  int kind;
+  double amp;
+  int nmodes;
+  double c[kMaxModes][3];
+  double m[kMaxModes][3];
+  int coef_kind;
+  double camp, f1, f2, phi1, phi2;
+};
+
+// Host data of one parameter direction.
+struct Dir1D {
+  int p = 0, q = 0, m = 0, n = 0, nel = 0;
+  std::vector<double> knots;
+  std::vector<int> elem_first;   // B-spline index (0-based) of the first function nonzero on element e
+  std::vector<double> qx, qw;    // [nel][q] Gauss points and weights
+  std::vector<double> val, der;  // [nel][q][p+1] values / derivatives of those functions
+  std::vector<double> M, K;      // n x n row-major
+  std::vector<double> U, lam;    // n x n row-major (U[i][k] = eigenvector k), n eigenvalues
+};
+
+igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1D* out);
+
+// Device copies of one direction.
+struct DevDir {
+  int n = 1, nel = 1, npad = 32;
+  int* elem_first = nullptr;
+  double* qx = nullptr;
+  double* qw = nullptr;
+  double* val = nullptr;
+  double* der = nullptr;
+  double* lam = nullptr;
+  double* W64[2] = {nullptr, nullptr};      // [0] = U^T (forward), [1] = U (backward), npad x npad
+  float* W32[2] = {nullptr, nullptr};
+  uint16_t* Wbf[2] = {nullptr, nullptr};
+  double* diagM = nullptr;
+  double* diagK = nullptr;
+};
+
+// CG scalars kept on the device so that iterations can be enqueued ahead.
+struct SolverState {
+  double bb, tol2;
+  double rho, pq, rr, rz, rzold, alpha, beta, rrtrue;
+  int iters, maxit, flag, flexible;
+};
+enum { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_MAXIT = 3 };
+
+}  // namespace igafd
+
+struct igafd_ctx {
+  int dim = 0, p = 0;
+  int n[3] = {1, 1, 1};
+  long long N = 0;
+  hipStream_t stream = nullptr;
+  igafd::GeomDesc geom{};
+  igafd::Dir1D dir[3];
+  igafd::DevDir ddir[3];
+  // symmetric band of A: plane h (0..H-1) holds the entries of offset
+  // center+h of the (2p+1)^d stencil, row-indexed; lower entries are read
+  // from the mirrored plane at the column row.
+  double* band = nullptr;
+  int H = 0;
+  long long Np = 0;
+  long long nnz = 0;
+  // workspace
+  double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *zold = nullptr;
+  double* fdbuf[2] = {nullptr, nullptr};   // FD intermediates (double or float)
+  double* scaling = nullptr;
+  bool scaling_set = false;
+  double* partial = nullptr;               // per-block partial sums
+  int npartial = 0;
+  igafd::SolverState* state = nullptr;     // device
+  igafd::SolverState* hstate = nullptr;    // pinned host mirror
+  int* dflag = nullptr;                    // device error flag (geometry)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace igafd {
+// assembly.hip
+igafd_status assemble_band(igafd_ctx* c);
+igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b);
+igafd_status diagonals(igafd_ctx* c, double* dA, double* dP);
+// spmv.hip
+igafd_status spmv(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
+int spmv_blocks(const igafd_ctx* c);
+// fd.hip
+igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
+                      double* partial_rz, const int* flag);
+int fd_dot_blocks(const igafd_ctx* c);
+int fd_npad(int n);
+}  // namespace igafd
