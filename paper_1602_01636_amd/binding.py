@@ -78,6 +78,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch ships its own HIP runtime (same soname).  Loading torch first makes
+        # the library bind to that runtime instead of pulling a second copy into
+        # the process, so both see the same device, streams and allocations.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             f = getattr(L, name)

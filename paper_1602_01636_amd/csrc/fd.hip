@@ -39,23 +39,30 @@ __device__ inline short to_bf16(float f) {
   return (short)(u >> 16);
 }
 
+// Operand layouts (checked on gfx950): A lane l holds row l%16, B lane l holds
+// column l%16, both with contracted index KPL*(l/16) + j.  Result register r
+// of lane l holds column l%16 and row 4*(l/16) + r for the f32 results, but
+// row l/16 + 4*r for the f64 result (ROW_STRIDE4).
 struct PF64 {
   using W = double;
   using acc = d4_t;
   static constexpr int KS = 4;
   static constexpr int KPL = 1;  // contracted-index values per lane per K-step
+  static constexpr bool ROW_STRIDE4 = true;
 };
 struct PF32 {
   using W = float;
   using acc = f4_t;
   static constexpr int KS = 4;
   static constexpr int KPL = 1;
+  static constexpr bool ROW_STRIDE4 = false;
 };
 struct PBF16 {
   using W = short;
   using acc = f4_t;
   static constexpr int KS = 16;
   static constexpr int KPL = 4;
+  static constexpr bool ROW_STRIDE4 = false;
 };
 
 enum { EPI_LAMBDA = 1, EPI_PRESCALE = 2, EPI_POSTSCALE = 4, EPI_DOT = 8 };
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout
   for (int t = 0; t < MT; ++t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int k = k0 + t * 16 + grp * 4 + r;
+      const int k = k0 + t * 16 + (Pr::ROW_STRIDE4 ? grp + 4 * r : grp * 4 + r);
       if (k < n && cok) {
         double v = (double)accv[t][r];
         const long long addr = TRX ? (long long)c * n + k : boff + (long long)k * C + c;
