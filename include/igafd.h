@@ -139,12 +139,27 @@ typedef struct {
   double true_relres;          /* ||b - A u||/||b|| evaluated in FP64 at exit                   */
   int status;                  /* igafd_status of the solve                                    */
   double t_solve_ms;           /* device time of the whole solve (events on the ctx stream)    */
+  int fallback;                /* 1: the scaled preconditioner stagnated and plain P finished  */
 } igafd_solve_info;
 
 /* PCG for A u = b preconditioned by P (or S P^-1 S).  b_dev, u_dev: N doubles.
  * Returns IGAFD_OK, IGAFD_NOT_CONVERGED (u holds the last iterate) or an error. */
 igafd_status igafd_solve(igafd_ctx* ctx, const double* b_dev, double* u_dev,
                          const igafd_solve_opts* opts, igafd_solve_info* info);
+
+/* Independent problems solved together (the batch workload): contexts are
+ * bound to a pool of streams for the duration of the call; each chunk of
+ * check_every iterations of all running problems is captured into one HIP
+ * graph and replayed until every problem has converged (re-captured when
+ * problems finish).  b[i], u[i]: device vectors of ctxs[i]; x0 = 0.
+ * infos (count entries) and wall_ms (device time of the CG loops) optional. */
+igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double* const* b, double* const* u,
+                                 const igafd_solve_opts* opts, igafd_solve_info* infos, double* wall_ms);
+
+/* Kernel shape of one problem: fd_tiles (16-row tiles per wave in the mode
+ * products, 1..8) and spmv_rows (rows per thread of the A product: 1, 2, 4).
+ * Zero for both: time the candidates on this problem and keep the fastest. */
+igafd_status igafd_autotune(igafd_ctx* ctx, int fd_tiles, int spmv_rows);
 
 /* Diagonals of A and P (N doubles each, device; either may be NULL). */
 igafd_status igafd_diagonals(igafd_ctx* ctx, double* diagA_dev, double* diagP_dev);
@@ -158,6 +173,49 @@ igafd_status igafd_get_eigen(const igafd_ctx* ctx, int dir, double* U_host, doub
  * is written to *n_out.  Needs no GPU. */
 igafd_status igafd_univariate(int degree, int nknots, const double* knots, int quad,
                               double* M, double* K, double* U, double* lam, int* n_out);
+
+/* ---------------- learned diagonal scaling (S P^-1 S) ----------------
+ * The paper notes that P degrades when Q varies strongly over the domain
+ * (Sec. 3, remarks after Prop. 1).  A small network predicts a diagonal S from
+ * local geometry/coefficient statistics; the solver then uses S P^-1 S, with
+ * plain P as the fallback when the scaled solve fails to converge.
+ */
+
+/* Per-dof inputs, N x 8 FP32 (device): the B_i-weighted quadrature averages
+ * over supp B_i of the entries (11, 22, 33, 12, 13, 23) of |det J| J^-1 J^-T
+ * and of kappa, then the degree p. */
+igafd_status igafd_features(igafd_ctx* ctx, float* feat_dev);
+
+/* Training targets t_i = 1/2 log(P_ii / A_ii) (N floats, device). */
+igafd_status igafd_scaling_targets(igafd_ctx* ctx, float* t_dev);
+
+/* Sets the scaling to the exact diagonal ratio S_i = (P_ii / A_ii)^(1/2)
+ * (the quantity the network learns; reference point for its gain). */
+igafd_status igafd_set_scaling_diag_ratio(igafd_ctx* ctx);
+
+/* Network 8 -> 64 -> 64 -> 1 (tanh), BF16 weights with FP32 accumulation on
+ * MFMA, FP32 master weights, Adam.  Parameters (igafd_mlp_num_params floats)
+ * are W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3, followed in the
+ * get/set arrays by the input normalisation mean[8], 1/std[8].  Calls are
+ * ordered on `stream`; the object owns its device buffers. */
+typedef struct igafd_mlp igafd_mlp;
+int igafd_mlp_num_params(void);
+igafd_status igafd_mlp_create(unsigned long long seed, void* stream, igafd_mlp** out);
+void igafd_mlp_destroy(igafd_mlp* mlp);
+/* input normalisation from n feature rows (device, n x 8) */
+igafd_status igafd_mlp_fit_normalization(igafd_mlp* mlp, const float* feat_dev, long long n);
+/* host arrays of igafd_mlp_num_params() + 16 floats */
+igafd_status igafd_mlp_get_params(const igafd_mlp* mlp, float* host);
+igafd_status igafd_mlp_set_params(igafd_mlp* mlp, const float* host);
+/* t = MLP(feat) (n floats, optional) and S = exp(t) (n doubles, optional), device */
+igafd_status igafd_mlp_forward(igafd_mlp* mlp, const float* feat_dev, long long n, float* t_dev, double* S_dev);
+/* gradient of L = (1/n) sum (t - target)^2 w.r.t. the parameters (host array of
+ * igafd_mlp_num_params floats) and L; no update */
+igafd_status igafd_mlp_gradient(igafd_mlp* mlp, const float* feat_dev, const float* target_dev, long long n,
+                                float* grad_host, float* loss_host);
+/* one Adam step on the minibatch (feat n x 8, target n); loss_host optional (syncs) */
+igafd_status igafd_mlp_train_step(igafd_mlp* mlp, const float* feat_dev, const float* target_dev, long long n,
+                                  float lr, float* loss_host);
 
 void igafd_destroy(igafd_ctx* ctx);
 const char* igafd_last_error(void);

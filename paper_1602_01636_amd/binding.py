@@ -48,7 +48,7 @@ class igafd_solve_opts(C.Structure):
 
 class igafd_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("relres", C.c_double), ("true_relres", C.c_double),
-                ("status", C.c_int), ("t_solve_ms", C.c_double)]
+                ("status", C.c_int), ("t_solve_ms", C.c_double), ("fallback", C.c_int)]
 
 
 _lib = None
@@ -69,6 +69,21 @@ _SIGNATURES = {
                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]),
     "igafd_destroy": (None, [C.c_void_p]),
     "igafd_last_error": (C.c_char_p, []),
+    "igafd_features": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(igafd_solve_opts),
+                                      C.c_void_p, C.POINTER(C.c_double)]),
+    "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "igafd_scaling_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_set_scaling_diag_ratio": (C.c_int, [C.c_void_p]),
+    "igafd_mlp_num_params": (C.c_int, []),
+    "igafd_mlp_create": (C.c_int, [C.c_ulonglong, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "igafd_mlp_destroy": (None, [C.c_void_p]),
+    "igafd_mlp_fit_normalization": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong]),
+    "igafd_mlp_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_mlp_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p]),
+    "igafd_mlp_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p]),
+    "igafd_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong, C.c_float, C.c_void_p]),
 }
 
 
@@ -109,6 +124,15 @@ def _dptr(t, N=None, name="vector"):
         raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
     if N is not None and t.numel() != N:
         raise ValueError(f"{name} has {t.numel()} elements, expected {N}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _fptr(t, n=None, name="array", cols=1):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n * cols:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n * cols}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -243,10 +267,44 @@ def igafd_solve(ctx: Context, b, u, rtol=1e-8, maxit=2000, precision="fp64", fle
     info = igafd_solve_info()
     st = _check(lib().igafd_solve(_h(ctx), _dptr(b, ctx.N, "b"), _dptr(u, ctx.N, "u"), C.byref(o), C.byref(info)))
     out = {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
-           "true_relres": info.true_relres, "status": STATUS_NAMES.get(st, st), "t_solve_ms": info.t_solve_ms}
+           "true_relres": info.true_relres, "status": STATUS_NAMES.get(st, st), "t_solve_ms": info.t_solve_ms,
+           "fallback": bool(info.fallback)}
     if hist is not None:
         out["history"] = hist[: info.iters + 1].copy()
     return out
+
+
+def _opts(rtol, maxit, precision, flexible, use_scaling, check_every, x0):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if flexible is None:
+        flexible = prec != IGAFD_FP64
+    o = igafd_solve_opts()
+    o.rtol, o.maxit, o.precision, o.flexible = float(rtol), int(maxit), prec, int(bool(flexible))
+    o.use_scaling, o.check_every, o.use_x0 = int(bool(use_scaling)), int(check_every), int(bool(x0))
+    return o
+
+
+def igafd_solve_batched(ctxs, bs, us, rtol=1e-8, maxit=2000, precision="fp64", flexible=None, use_scaling=False,
+                        check_every=4):
+    """Solve len(ctxs) independent problems together; returns (infos, wall_ms)."""
+    n = len(ctxs)
+    if not (len(bs) == len(us) == n) or n == 0:
+        raise ValueError("need one b and one u per context")
+    H = (C.c_void_p * n)(*[_h(c) for c in ctxs])
+    Bp = (C.c_void_p * n)(*[_dptr(b, c.N, "b").value for b, c in zip(bs, ctxs)])
+    Up = (C.c_void_p * n)(*[_dptr(u, c.N, "u").value for u, c in zip(us, ctxs)])
+    infos = (igafd_solve_info * n)()
+    wall = C.c_double()
+    o = _opts(rtol, maxit, precision, flexible, use_scaling, check_every, False)
+    _check(lib().igafd_solve_batched(H, n, Bp, Up, C.byref(o), infos, C.byref(wall)))
+    out = [{"iters": i.iters, "restarts": i.restarts, "relres": i.relres, "true_relres": i.true_relres,
+            "status": STATUS_NAMES.get(i.status, i.status)} for i in infos]
+    return out, wall.value
+
+
+def igafd_autotune(ctx: Context, fd_tiles=0, spmv_rows=0):
+    """Kernel shape of one problem (0, 0: time the candidates and keep the fastest)."""
+    _check(lib().igafd_autotune(_h(ctx), int(fd_tiles), int(spmv_rows)))
 
 
 def igafd_get_eigen(ctx: Context, direction: int):
@@ -278,3 +336,98 @@ def igafd_destroy(ctx):
         ctx.close()
     elif ctx:
         lib().igafd_destroy(ctx)
+
+
+# ---------------- learned diagonal scaling ----------------
+
+def igafd_features(ctx: Context, feat):
+    """Per-dof network inputs into feat (float32, N x 8)."""
+    _check(lib().igafd_features(_h(ctx), _fptr(feat, ctx.N, "feat", 8)))
+
+
+def igafd_scaling_targets(ctx: Context, t):
+    """t_i = 1/2 log(P_ii / A_ii) into t (float32, N)."""
+    _check(lib().igafd_scaling_targets(_h(ctx), _fptr(t, ctx.N, "targets")))
+
+
+def igafd_set_scaling_diag_ratio(ctx: Context):
+    """Scaling S_i = (P_ii / A_ii)^(1/2) set on the context."""
+    _check(lib().igafd_set_scaling_diag_ratio(_h(ctx)))
+
+
+def igafd_mlp_num_params() -> int:
+    return int(lib().igafd_mlp_num_params())
+
+
+class Mlp:
+    """Owner of an igafd_mlp handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().igafd_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def igafd_mlp_create(seed=0, stream=None) -> Mlp:
+    h = C.c_void_p()
+    _check(lib().igafd_mlp_create(int(seed), stream if stream is not None else _current_stream(), C.byref(h)))
+    return Mlp(h)
+
+
+def igafd_mlp_destroy(m: Mlp):
+    m.close()
+
+
+def igafd_mlp_fit_normalization(m: Mlp, feat, n):
+    _check(lib().igafd_mlp_fit_normalization(m.handle, _fptr(feat, n, "feat", 8), int(n)))
+
+
+def igafd_mlp_get_params(m: Mlp) -> np.ndarray:
+    out = np.zeros(igafd_mlp_num_params() + 16, dtype=np.float32)
+    _check(lib().igafd_mlp_get_params(m.handle, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def igafd_mlp_set_params(m: Mlp, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != igafd_mlp_num_params() + 16:
+        raise ValueError("parameter array has the wrong length")
+    _check(lib().igafd_mlp_set_params(m.handle, a.ctypes.data_as(C.c_void_p)))
+
+
+def igafd_mlp_forward(m: Mlp, feat, n, t=None, S=None):
+    tp = None if t is None else _fptr(t, n, "t")
+    if S is not None:
+        _dptr(S, n, "S")
+    Sp = None if S is None else C.c_void_p(S.data_ptr())
+    _check(lib().igafd_mlp_forward(m.handle, _fptr(feat, n, "feat", 8), int(n), tp, Sp))
+
+
+def igafd_mlp_gradient(m: Mlp, feat, target, n):
+    g = np.zeros(igafd_mlp_num_params(), dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(lib().igafd_mlp_gradient(m.handle, _fptr(feat, n, "feat", 8), _fptr(target, n, "target"), int(n),
+                                    g.ctypes.data_as(C.c_void_p), loss.ctypes.data_as(C.c_void_p)))
+    return float(loss[0]), g
+
+
+def igafd_mlp_train_step(m: Mlp, feat, target, n, lr, want_loss=False):
+    loss = np.zeros(1, dtype=np.float32)
+    _check(lib().igafd_mlp_train_step(m.handle, _fptr(feat, n, "feat", 8), _fptr(target, n, "target"), int(n),
+                                      float(lr), loss.ctypes.data_as(C.c_void_p) if want_loss else None))
+    return float(loss[0]) if want_loss else None

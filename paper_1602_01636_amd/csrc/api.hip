@@ -14,6 +14,7 @@
 // not meet the tolerance.  flexible = 1 uses the Polak-Ribiere beta
 // (r_{k+1}, z_{k+1} - z_k) / (r_k, z_k) for inexact (FP32/BF16) applies.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -306,7 +307,12 @@ igafd_status alloc_workspace(igafd_ctx* c) {
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->r, vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->z, vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->zold, vb));
-  IGAFD_HIP_CHECK(hipMalloc((void**)&c->pv, vb));
+  const size_t pb = sizeof(double) * (size_t)c->Ns;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->pv_pad, pb));
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->xpad, pb));
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->pv_pad, 0, pb, c->stream));
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->xpad, 0, pb, c->stream));
+  c->pv = c->pv_pad + c->halo;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->q, vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[0], vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[1], vb));
@@ -356,31 +362,58 @@ igafd_status start_directions(igafd_ctx* c, int prec, const double* S, double*& 
   return IGAFD_OK;
 }
 
-igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_solve_opts* o, igafd_solve_info* info) {
-  const int maxit = o->maxit > 0 ? o->maxit : 2000;
-  const int chunk = o->check_every > 0 ? o->check_every : 4;
-  const int prec = o->precision;
-  const int flexible = o->flexible ? 1 : 0;
-  if (prec != IGAFD_FP64 && !flexible) {
+// One CG iteration, enqueued without any host synchronisation (also used
+// under graph capture).  z / zold swap roles every iteration.
+igafd_status enqueue_iteration(igafd_ctx* c, double* x, int prec, const double* S, int flexible, double*& z,
+                               double*& zold, double* hist) {
+  const unsigned vb = vblocks(c);
+  const int* flag = &c->state->flag;
+  // q = A p, (p, q)
+  IGAFD_TRY(spmv(c, c->pv, c->q, c->partial, flag));
+  IGAFD_TRY(reduce(c, spmv_blocks(c), 0, RED_PQ, hist));
+  // x += alpha p, r -= alpha q, (r, r) [, (r, z_old)]
+  hipLaunchKernelGGL(k_update_xr, dim3(vb), dim3(kBlock), 0, c->stream, x, c->r, c->pv, c->q, flexible ? z : nullptr,
+                     c->state, c->N, c->partial);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  IGAFD_TRY(reduce(c, (int)vb, flexible, RED_RR, hist));
+  // z = M r, (r, z) -> beta; the previous z stays as z_old for the flexible form
+  std::swap(z, zold);
+  IGAFD_TRY(precond_step(c, prec, S, z, RED_RZ, flag));
+  hipLaunchKernelGGL(k_update_p, dim3(vb), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 0, c->N);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+igafd_status check_opts(const igafd_ctx* c, const igafd_solve_opts* o) {
+  if (o->precision != IGAFD_FP64 && !o->flexible) {
     set_error("FP32/BF16 preconditioner applies need the flexible CG form");
+    return IGAFD_ERR_ARG;
+  }
+  if (o->precision < IGAFD_FP64 || o->precision > IGAFD_BF16) {
+    set_error("unknown precision");
     return IGAFD_ERR_ARG;
   }
   if (!(o->rtol > 0.0)) {
     set_error("rtol must be positive");
     return IGAFD_ERR_ARG;
   }
-  const double* S = nullptr;
-  if (o->use_scaling) {
-    if (!c->scaling_set) {
-      set_error("use_scaling requested but no scaling set");
-      return IGAFD_ERR_ARG;
-    }
-    S = c->scaling;
+  if (o->use_scaling && !c->scaling_set) {
+    set_error("use_scaling requested but no scaling set");
+    return IGAFD_ERR_ARG;
   }
+  return IGAFD_OK;
+}
+
+igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_solve_opts* o, igafd_solve_info* info) {
+  const int maxit = o->maxit > 0 ? o->maxit : 2000;
+  const int chunk = o->check_every > 0 ? o->check_every : 4;
+  const int prec = o->precision;
+  const int flexible = o->flexible ? 1 : 0;
+  IGAFD_TRY(check_opts(c, o));
+  const double* S = o->use_scaling ? c->scaling : nullptr;
   double* hist = nullptr;
   if (o->history) IGAFD_HIP_CHECK(hipMalloc((void**)&hist, sizeof(double) * (maxit + 1)));
   const unsigned vb = vblocks(c);
-  const int* flag = &c->state->flag;
   IGAFD_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
 
   SolverState init{};
@@ -391,7 +424,7 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
   IGAFD_HIP_CHECK(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
   const double* y = nullptr;
   if (o->use_x0) {
-    IGAFD_TRY(spmv(c, x, c->q, nullptr, nullptr));
+    IGAFD_TRY(spmv_unpadded(c, x, c->q, nullptr, nullptr));
     y = c->q;
   }
   hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, b, y, c->r, x, o->use_x0 ? 1 : 0, c->N, c->partial);
@@ -402,49 +435,43 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
 
   double* z = c->z;
   double* zold = c->zold;
-  int restarts = 0;
+  int restarts = 0, fell_back = 0;
   double true_rel = 0.0;
   int status = IGAFD_OK;
   while (true) {
     if (c->hstate->flag == FLAG_RUNNING) {
       IGAFD_TRY(start_directions(c, prec, S, z, zold));
       while (true) {
-        for (int k = 0; k < chunk; ++k) {
-          // q = A p, (p, q)
-          IGAFD_TRY(spmv(c, c->pv, c->q, c->partial, flag));
-          IGAFD_TRY(reduce(c, spmv_blocks(c), 0, RED_PQ, hist));
-          // x += alpha p, r -= alpha q, (r, r) [, (r, z_old)]
-          hipLaunchKernelGGL(k_update_xr, dim3(vb), dim3(kBlock), 0, c->stream, x, c->r, c->pv, c->q,
-                             flexible ? z : nullptr, c->state, c->N, c->partial);
-          IGAFD_HIP_CHECK(hipGetLastError());
-          IGAFD_TRY(reduce(c, (int)vb, flexible, RED_RR, hist));
-          // z = M r, (r, z) -> beta; the previous z stays as z_old for the flexible form
-          std::swap(z, zold);
-          IGAFD_TRY(precond_step(c, prec, S, z, RED_RZ, flag));
-          hipLaunchKernelGGL(k_update_p, dim3(vb), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 0, c->N);
-          IGAFD_HIP_CHECK(hipGetLastError());
-        }
+        for (int k = 0; k < chunk; ++k) IGAFD_TRY(enqueue_iteration(c, x, prec, S, flexible, z, zold, hist));
         IGAFD_TRY(read_state(c));
         if (c->hstate->flag != FLAG_RUNNING) break;
       }
     }
     // true residual in FP64
-    IGAFD_TRY(spmv(c, x, c->q, nullptr, nullptr));
+    IGAFD_TRY(spmv_unpadded(c, x, c->q, nullptr, nullptr));
     hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, b, c->q, c->r, c->N, c->partial);
     IGAFD_HIP_CHECK(hipGetLastError());
     IGAFD_TRY(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
     IGAFD_TRY(read_state(c));
     const SolverState hs = *c->hstate;
     true_rel = bb > 0.0 ? std::sqrt(hs.rrtrue / bb) : 0.0;
-    if (hs.flag == FLAG_BREAKDOWN) {
-      status = IGAFD_ERR_BREAKDOWN;
-      break;
-    }
-    if (true_rel <= o->rtol) {
+    if (true_rel <= o->rtol && hs.flag != FLAG_BREAKDOWN) {
       status = IGAFD_OK;
       break;
     }
-    if (hs.iters >= maxit || restarts >= 3) {
+    const bool stuck = hs.flag == FLAG_BREAKDOWN || hs.iters >= c->hstate->maxit || restarts >= 3;
+    if (stuck && S && std::isfinite(true_rel)) {
+      // the scaled preconditioner stagnated or broke down: continue from the
+      // current iterate with plain P and a fresh iteration budget
+      S = nullptr;
+      fell_back = 1;
+      c->hstate->maxit = hs.iters + maxit;
+      IGAFD_HIP_CHECK(hipMemcpyAsync(&c->state->maxit, &c->hstate->maxit, sizeof(int), hipMemcpyHostToDevice,
+                                     c->stream));
+    } else if (hs.flag == FLAG_BREAKDOWN) {
+      status = IGAFD_ERR_BREAKDOWN;
+      break;
+    } else if (stuck) {
       status = IGAFD_NOT_CONVERGED;
       break;
     }
@@ -472,9 +499,252 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
     info->status = status;
     info->t_solve_ms = ms;
     info->relres = bb > 0.0 ? std::sqrt(hs.rr / bb) : 0.0;
+    info->fallback = fell_back;
   }
   if (status == IGAFD_ERR_BREAKDOWN) set_error("CG breakdown: p^T A p <= 0 or not finite");
   return (igafd_status)status;
+}
+
+// Several independent problems solved together: each context is bound to
+// one stream of a small pool, every chunk of iterations of all running
+// problems is captured once into a HIP graph (fork/join over the pool) and
+// replayed until all have converged; the graph is rebuilt when problems
+// finish.  Every kernel of a converged problem is a no-op (device stop flag).
+// Problems that fail the FP64 true-residual check continue alone.
+igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* const* bs, double* const* xs,
+                                const igafd_solve_opts* o, igafd_solve_info* infos, double* wall_ms) {
+  for (int i = 0; i < count; ++i) {
+    if (!cs[i] || !bs[i] || !xs[i] || bs[i] == xs[i]) {
+      set_error("batched solve needs a context and distinct b, u for every problem");
+      return IGAFD_ERR_ARG;
+    }
+    IGAFD_TRY(check_opts(cs[i], o));
+  }
+  const int maxit = o->maxit > 0 ? o->maxit : 2000;
+  int chunk = o->check_every > 0 ? o->check_every : 4;
+  chunk += chunk & 1;  // even: the z / z_old roles return to the captured ones
+  const int nst = count < 8 ? count : 8;
+  std::vector<hipStream_t> pool(nst, nullptr), saved(count);
+  std::vector<hipEvent_t> join(nst, nullptr);
+  hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  igafd_status st = IGAFD_OK;
+  std::vector<double*> z(count), zold(count);
+  std::vector<char> running(count, 0);
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (int k = 0; k < nst; ++k) {
+      if (pool[k]) (void)hipStreamSynchronize(pool[k]);
+    }
+    for (int i = 0; i < count; ++i) cs[i]->stream = saved[i];
+    for (int k = 0; k < nst; ++k) {
+      if (join[k]) (void)hipEventDestroy(join[k]);
+      if (pool[k]) (void)hipStreamDestroy(pool[k]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+#define IGAFD_BT(x)              \
+  do {                           \
+    if ((st = (x)) != IGAFD_OK) {\
+      cleanup();                 \
+      return st;                 \
+    }                            \
+  } while (0)
+#define IGAFD_BH(x)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess) {                                                      \
+      set_error(std::string(#x) + ": " + hipGetErrorString(e_));                 \
+      cleanup();                                                                 \
+      return IGAFD_ERR_HIP;                                                      \
+    }                                                                            \
+  } while (0)
+  for (int i = 0; i < count; ++i) saved[i] = cs[i]->stream;
+  for (int k = 0; k < nst; ++k) {
+    IGAFD_BH(hipStreamCreateWithFlags(&pool[k], hipStreamNonBlocking));
+    IGAFD_BH(hipEventCreateWithFlags(&join[k], hipEventDisableTiming));
+  }
+  IGAFD_BH(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  IGAFD_BH(hipEventCreate(&t0));
+  IGAFD_BH(hipEventCreate(&t1));
+  for (int i = 0; i < count; ++i) cs[i]->stream = pool[i % nst];
+  auto sync_all = [&]() -> igafd_status {
+    for (int k = 0; k < nst; ++k) IGAFD_HIP_CHECK(hipStreamSynchronize(pool[k]));
+    return IGAFD_OK;
+  };
+  IGAFD_BH(hipEventRecord(t0, pool[0]));
+  for (int k = 1; k < nst; ++k) IGAFD_BH(hipStreamWaitEvent(pool[k], t0, 0));
+  // init: r = b, x = 0, ||b||, ||r||; then the first directions
+  for (int i = 0; i < count; ++i) {
+    igafd_ctx* c = cs[i];
+    SolverState init{};
+    init.tol2 = o->rtol * o->rtol;
+    init.maxit = maxit;
+    init.flexible = o->flexible ? 1 : 0;
+    *c->hstate = init;
+    IGAFD_BH(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
+    const unsigned vb = vblocks(c);
+    hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], nullptr, c->r, xs[i], 0, c->N, c->partial);
+    IGAFD_BH(hipGetLastError());
+    IGAFD_BT(reduce(c, (int)vb, 1, RED_BB_RR, nullptr));
+    IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+  }
+  IGAFD_BT(sync_all());
+  for (int i = 0; i < count; ++i) {
+    igafd_ctx* c = cs[i];
+    z[i] = c->z;
+    zold[i] = c->zold;
+    running[i] = c->hstate->flag == FLAG_RUNNING;
+    if (running[i])
+      IGAFD_BT(start_directions(c, o->precision, o->use_scaling ? c->scaling : nullptr, z[i], zold[i]));
+  }
+  const bool use_graph = std::getenv("IGAFD_NO_GRAPH") == nullptr;
+  int captured_for = -1;
+  while (true) {
+    int nrun = 0;
+    for (int i = 0; i < count; ++i) nrun += running[i];
+    if (nrun == 0) break;
+    auto enqueue_chunk = [&]() -> igafd_status {
+      for (int k = 0; k < chunk; ++k)
+        for (int i = 0; i < count; ++i)
+          if (running[i])
+            IGAFD_TRY(enqueue_iteration(cs[i], xs[i], o->precision, o->use_scaling ? cs[i]->scaling : nullptr,
+                                        o->flexible ? 1 : 0, z[i], zold[i], nullptr));
+      return IGAFD_OK;
+    };
+    if (use_graph) {
+      if (captured_for != nrun) {  // (re)capture the chunk for the running set
+        if (exec) IGAFD_BH(hipGraphExecDestroy(exec));
+        if (graph) IGAFD_BH(hipGraphDestroy(graph));
+        exec = nullptr;
+        graph = nullptr;
+        IGAFD_BT(sync_all());
+        IGAFD_BH(hipStreamBeginCapture(pool[0], hipStreamCaptureModeRelaxed));
+        IGAFD_BH(hipEventRecord(fork, pool[0]));
+        for (int k = 1; k < nst; ++k) IGAFD_BH(hipStreamWaitEvent(pool[k], fork, 0));
+        st = enqueue_chunk();
+        for (int k = 1; k < nst; ++k) {
+          (void)hipEventRecord(join[k], pool[k]);
+          (void)hipStreamWaitEvent(pool[0], join[k], 0);
+        }
+        const hipError_t ec = hipStreamEndCapture(pool[0], &graph);
+        if (st != IGAFD_OK) {
+          cleanup();
+          return st;
+        }
+        IGAFD_BH(ec);
+        IGAFD_BH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        captured_for = nrun;
+      }
+      IGAFD_BH(hipGraphLaunch(exec, pool[0]));
+      for (int i = 0; i < count; ++i)
+        IGAFD_BH(hipMemcpyAsync(cs[i]->hstate, cs[i]->state, sizeof(SolverState), hipMemcpyDeviceToHost, pool[0]));
+    } else {
+      IGAFD_BT(enqueue_chunk());
+      for (int i = 0; i < count; ++i)
+        IGAFD_BH(hipMemcpyAsync(cs[i]->hstate, cs[i]->state, sizeof(SolverState), hipMemcpyDeviceToHost,
+                                cs[i]->stream));
+    }
+    IGAFD_BT(sync_all());
+    for (int i = 0; i < count; ++i) running[i] = running[i] && cs[i]->hstate->flag == FLAG_RUNNING;
+  }
+  for (int k = 1; k < nst; ++k) IGAFD_BH(hipStreamWaitEvent(pool[0], join[k], 0));
+  IGAFD_BH(hipEventRecord(t1, pool[0]));
+  IGAFD_BT(sync_all());
+  float ms = 0.f;
+  IGAFD_BH(hipEventElapsedTime(&ms, t0, t1));
+  if (wall_ms) *wall_ms = ms;
+  // FP64 true residuals; a problem that misses the tolerance continues alone
+  for (int i = 0; i < count; ++i) {
+    igafd_ctx* c = cs[i];
+    const unsigned vb = vblocks(c);
+    IGAFD_BT(spmv_unpadded(c, xs[i], c->q, nullptr, nullptr));
+    hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], c->q, c->r, c->N, c->partial);
+    IGAFD_BH(hipGetLastError());
+    IGAFD_BT(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
+    IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+  }
+  IGAFD_BT(sync_all());
+  for (int i = 0; i < count; ++i) {
+    igafd_ctx* c = cs[i];
+    const SolverState hs = *c->hstate;
+    const double rel = hs.bb > 0.0 ? std::sqrt(hs.rrtrue / hs.bb) : 0.0;
+    igafd_solve_info inf{};
+    inf.iters = hs.iters;
+    inf.relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+    inf.true_relres = rel;
+    inf.t_solve_ms = ms;
+    inf.status = hs.flag == FLAG_BREAKDOWN ? IGAFD_ERR_BREAKDOWN : IGAFD_OK;
+    if (!(rel <= o->rtol) && hs.flag != FLAG_BREAKDOWN) {
+      igafd_solve_opts oc = *o;
+      oc.use_x0 = 1;
+      oc.maxit = maxit > hs.iters ? maxit - hs.iters : 1;
+      oc.history = nullptr;
+      igafd_solve_info more{};
+      const igafd_status s2 = solve_impl(c, bs[i], xs[i], &oc, &more);
+      inf.iters = hs.iters + more.iters;
+      inf.restarts = 1 + more.restarts;
+      inf.true_relres = more.true_relres;
+      inf.relres = more.relres;
+      inf.status = s2;
+    }
+    if (infos) infos[i] = inf;
+  }
+  cleanup();
+  for (int i = 0; i < count; ++i)
+    if (infos && infos[i].status < 0) return (igafd_status)infos[i].status;
+#undef IGAFD_BT
+#undef IGAFD_BH
+  return IGAFD_OK;
+}
+
+// Tile choice for one problem: time the FD apply for 1..4 row tiles per wave
+// and the A product for 1, 2, 4 rows per thread; keep the fastest.
+igafd_status autotune_impl(igafd_ctx* c, int reps) {
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->r, 0, sizeof(double) * c->N, c->stream));
+  hipEvent_t a, b;
+  IGAFD_HIP_CHECK(hipEventCreate(&a));
+  IGAFD_HIP_CHECK(hipEventCreate(&b));
+  auto time_it = [&](auto fn) -> float {
+    fn();
+    (void)hipEventRecord(a, c->stream);
+    for (int k = 0; k < reps; ++k) fn();
+    (void)hipEventRecord(b, c->stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  };
+  float best = 1e30f;
+  int best_t = c->fd_tiles;
+  for (int t = 1; t <= 4; ++t) {
+    c->fd_tiles = t;
+    const float ms = time_it([&]() { (void)fd_apply(c, IGAFD_FP64, c->r, c->z, nullptr, nullptr, nullptr); });
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  c->fd_tiles = best_t;
+  best = 1e30f;
+  int best_r = c->spmv_rows;
+  for (int r : {1, 2, 4}) {
+    c->spmv_rows = r;
+    const float ms = time_it([&]() { (void)spmv(c, c->pv, c->q, nullptr, nullptr); });
+    if (ms < best) {
+      best = ms;
+      best_r = r;
+    }
+  }
+  c->spmv_rows = best_r;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
 }
 
 }  // namespace
@@ -508,7 +778,8 @@ void igafd_destroy(igafd_ctx* c) {
   free_dev(c->r);
   free_dev(c->z);
   free_dev(c->zold);
-  free_dev(c->pv);
+  free_dev(c->pv_pad);
+  free_dev(c->xpad);
   free_dev(c->q);
   free_dev(c->fdbuf[0]);
   free_dev(c->fdbuf[1]);
@@ -550,9 +821,15 @@ igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out)
   const int W = 2 * c->p + 1;
   const int Sz = (c->dim == 3) ? W * W * W : W * W;
   c->H = (Sz + 1) / 2;
-  c->Np = (c->N + 63) / 64 * 64;
+  // zero halo: the largest stencil offset, rounded to 64 rows
+  const long long maxoff = (long long)c->p * (1 + c->n[0] + (c->dim == 3 ? (long long)c->n[0] * c->n[1] : 0));
+  c->halo = (maxoff + 63) / 64 * 64;
+  c->Ns = (c->N + 2 * c->halo + 8 + 63) / 64 * 64;
   c->nnz = band_nnz(c.get());
-  IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Np));
+  if (const char* e = std::getenv("IGAFD_SPMV_ROWS")) c->spmv_rows = std::atoi(e);
+  if (const char* e = std::getenv("IGAFD_FD_TILES")) c->fd_tiles = std::atoi(e);
+  if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
   if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
   if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -569,7 +846,7 @@ igafd_status igafd_sizes(const igafd_ctx* c, int n[3], long long* N, long long* 
     for (int l = 0; l < 3; ++l) n[l] = c->n[l];
   if (N) *N = c->N;
   if (nnz) *nnz = c->nnz;
-  if (band_bytes) *band_bytes = (long long)sizeof(double) * c->H * c->Np;
+  if (band_bytes) *band_bytes = (long long)sizeof(double) * c->H * c->Ns;
   return IGAFD_OK;
 }
 
@@ -586,7 +863,7 @@ igafd_status igafd_apply_A(igafd_ctx* c, const double* x, double* y) {
     set_error("apply_A needs distinct non-null vectors");
     return IGAFD_ERR_ARG;
   }
-  return spmv(c, x, y, nullptr, nullptr);
+  return spmv_unpadded(c, x, y, nullptr, nullptr);
 }
 
 igafd_status igafd_apply_precond(igafd_ctx* c, int precision, const double* r, double* s) {
@@ -620,6 +897,33 @@ igafd_status igafd_diagonals(igafd_ctx* c, double* dA, double* dP) {
   return diagonals(c, dA, dP);
 }
 
+igafd_status igafd_features(igafd_ctx* c, float* feat) {
+  if (!c || !feat) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  return features(c, feat);
+}
+
+igafd_status igafd_scaling_targets(igafd_ctx* c, float* t) {
+  if (!c || !t) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  return scaling_targets(c, t);
+}
+
+igafd_status igafd_set_scaling_diag_ratio(igafd_ctx* c) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (!c->scaling) IGAFD_HIP_CHECK(hipMalloc((void**)&c->scaling, sizeof(double) * c->N));
+  igafd_status st = diag_ratio_scaling(c, c->scaling);
+  if (st == IGAFD_OK) c->scaling_set = true;
+  return st;
+}
+
 igafd_status igafd_get_eigen(const igafd_ctx* c, int dir, double* U, double* lam) {
   if (!c || dir < 0 || dir >= c->dim) {
     set_error("bad context or direction");
@@ -629,6 +933,32 @@ igafd_status igafd_get_eigen(const igafd_ctx* c, int dir, double* U, double* lam
   if (U) std::memcpy(U, d.U.data(), sizeof(double) * d.U.size());
   if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * d.lam.size());
   return IGAFD_OK;
+}
+
+igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double* const* b, double* const* u,
+                                 const igafd_solve_opts* o, igafd_solve_info* infos, double* wall_ms) {
+  if (!ctxs || !b || !u || !o || count < 1) {
+    set_error("batched solve needs count >= 1 contexts, vectors and options");
+    return IGAFD_ERR_ARG;
+  }
+  return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
+}
+
+igafd_status igafd_autotune(igafd_ctx* c, int fd_tiles, int spmv_rows) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (fd_tiles > 0 || spmv_rows > 0) {  // explicit choice
+    if (fd_tiles > 8 || spmv_rows > 4 || spmv_rows == 3) {
+      set_error("fd_tiles must be 1..8 and spmv_rows 1, 2 or 4");
+      return IGAFD_ERR_ARG;
+    }
+    if (fd_tiles > 0) c->fd_tiles = fd_tiles;
+    if (spmv_rows > 0) c->spmv_rows = spmv_rows;
+    return IGAFD_OK;
+  }
+  return autotune_impl(c, 3);
 }
 
 igafd_status igafd_solve(igafd_ctx* c, const double* b, double* u, const igafd_solve_opts* o, igafd_solve_info* info) {

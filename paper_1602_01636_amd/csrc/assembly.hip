@@ -102,7 +102,7 @@ __host__ __device__ constexpr int sym_index(int a, int b) {
 
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, double* __restrict__ band,
-                                                     long long Np, int c1, int c2, int c3, int m1, int m2,
+                                                     long long Ns, int c1, int c2, int c3, int m1, int m2,
                                                      int* __restrict__ err) {
   constexpr int Q = P + 1, L = P + 1;
   constexpr int Q3 = (D == 3) ? Q : 1;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
         }
         const int oidx = ((o3 + R3) * W + (o2 + P)) * W + (o1 + P);
         const long long row = r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3);
-        band[(long long)(oidx - CENTER) * Np + row] += s;
+        band[(long long)(oidx - CENTER) * Ns + row] += s;
       }
       __syncthreads();
     }
@@ -303,6 +303,99 @@ __global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, int rhs_k
   }
 }
 
+// Per-dof geometry/coefficient statistics for the learned scaling: the
+// B_i-weighted quadrature averages over supp B_i of the six entries of
+// G = |det J| J^-1 J^-T (= Q / kappa, Sec. 2.1 eq. Q) and of kappa.  One colour
+// class of elements adds w_t B_i(t) (G_c(t), kappa(t), 1) into acc[i][0..7].
+template <int D, int P>
+__global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, double* __restrict__ acc, int c1, int c2,
+                                                     int c3, int m1, int m2) {
+  constexpr int Q = P + 1, L = P + 1;
+  constexpr int Q3 = (D == 3) ? Q : 1;
+  constexpr int L3 = (D == 3) ? L : 1;
+  constexpr int NQ = Q * Q * Q3;
+  __shared__ double sf[8][NQ];
+  __shared__ double sV[3][Q][L];
+  int bid = blockIdx.x;
+  const int j1 = bid % m1;
+  bid /= m1;
+  const int j2 = bid % m2;
+  const int j3 = bid / m2;
+  const int e[3] = {c1 + j1 * (P + 1), c2 + j2 * (P + 1), (D == 3) ? c3 + j3 * (P + 1) : 0};
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 3 * Q * L; idx += kBlock) {
+    const int l = idx / (Q * L), t = (idx / L) % Q, a = idx % L;
+    sV[l][t][a] = (l < D) ? T.val[l][(e[l] * Q + t) * L + a] : ((t == 0 && a == 0) ? 1.0 : 0.0);
+  }
+  for (int t = tid; t < NQ; t += kBlock) {
+    const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
+    double xi[3] = {T.qx[0][e[0] * Q + t1], T.qx[1][e[1] * Q + t2], 0.0};
+    double w = T.qw[0][e[0] * Q + t1] * T.qw[1][e[1] * Q + t2];
+    if (D == 3) {
+      xi[2] = T.qx[2][e[2] * Q + t3];
+      w *= T.qw[2][e[2] * Q + t3];
+    }
+    double x[3], J[3][3], A[3][3] = {};
+    map_eval<D>(g, xi, x, J);
+    const double det = fabs(adjugate<D>(J, A));
+    double G[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s += A[a][k] * A[b][k];
+        G[a][b] = (a < D && b < D) ? s / det : 0.0;
+      }
+    sf[0][t] = w * G[0][0];
+    sf[1][t] = w * G[1][1];
+    sf[2][t] = w * G[2][2];
+    sf[3][t] = w * G[0][1];
+    sf[4][t] = w * G[0][2];
+    sf[5][t] = w * G[1][2];
+    sf[6][t] = w * kappa_eval(g, x);
+    sf[7][t] = w;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < L * L * L3; idx += kBlock) {
+    const int a1 = idx % L, a2 = (idx / L) % L, a3 = idx / (L * L);
+    const int r1 = T.first[0][e[0]] + a1 - 1, r2 = T.first[1][e[1]] + a2 - 1;
+    const int r3 = (D == 3) ? T.first[2][e[2]] + a3 - 1 : 0;
+    if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < NQ; ++t) {
+      const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
+      const double bv = sV[0][t1][a1] * sV[1][t2][a2] * sV[2][t3][a3];
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) s[ch] += sf[ch][t] * bv;
+    }
+    double* o = acc + 8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3));
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) o[ch] += s[ch];
+  }
+}
+
+// feat[i] = (acc[i][0..6] / acc[i][7], p) in FP32
+__global__ void k_features_finish(const double* __restrict__ acc, float* __restrict__ feat, long long N, int p) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double inv = 1.0 / acc[8 * i + 7];
+  for (int ch = 0; ch < 7; ++ch) feat[8 * i + ch] = (float)(acc[8 * i + ch] * inv);
+  feat[8 * i + 7] = (float)p;
+}
+
+// S_i = sqrt(P_ii / A_ii): the diagonal-ratio scaling
+__global__ void k_sqrt_ratio(const double* __restrict__ band0, const double* __restrict__ dP, double* __restrict__ S,
+                             long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) S[i] = sqrt(dP[i] / band0[i]);
+}
+
+// t_i = 1/2 log(P_ii / A_ii): the log of the diagonal-ratio scaling
+__global__ void k_log_ratio(const double* __restrict__ band0, const double* __restrict__ dP, float* __restrict__ t,
+                            long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) t[i] = (float)(0.5 * log(dP[i] / band0[i]));
+}
+
 // diag(P) = sum_j K_j[i_j, i_j] prod_{l != j} M_l[i_l, i_l]  (Sec. 3 Kronecker sum)
 __global__ void k_diagP(const double* m1, const double* k1, const double* m2, const double* k2,
                         const double* m3, const double* k3, int n1, int n2, long long N, int dim,
@@ -350,7 +443,7 @@ igafd_status launch_assemble(igafd_ctx* c) {
         const long long blocks = (long long)m1 * m2 * m3;
         if (blocks == 0) continue;
         hipLaunchKernelGGL((k_assemble<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom,
-                           c->band, c->Np, c1, c2, c3, m1, m2, c->dflag);
+                           c->band + c->halo, c->Ns, c1, c2, c3, m1, m2, c->dflag);
         IGAFD_HIP_CHECK(hipGetLastError());
       }
   return IGAFD_OK;
@@ -376,6 +469,26 @@ igafd_status launch_load(igafd_ctx* c, int rhs_kind, double* b) {
   return IGAFD_OK;
 }
 
+template <int D, int P>
+igafd_status launch_features(igafd_ctx* c, double* acc) {
+  const Tables T = make_tables(c);
+  const int nel[3] = {c->ddir[0].nel, c->ddir[1].nel, D == 3 ? c->ddir[2].nel : 1};
+  const int C3 = (D == 3) ? P + 1 : 1;
+  for (int c3 = 0; c3 < C3; ++c3)
+    for (int c2 = 0; c2 <= P; ++c2)
+      for (int c1 = 0; c1 <= P; ++c1) {
+        const int m1 = c1 < nel[0] ? (nel[0] - c1 + P) / (P + 1) : 0;
+        const int m2 = c2 < nel[1] ? (nel[1] - c2 + P) / (P + 1) : 0;
+        const int m3 = (D == 3) ? (c3 < nel[2] ? (nel[2] - c3 + P) / (P + 1) : 0) : 1;
+        const long long blocks = (long long)m1 * m2 * m3;
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL((k_features<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom, acc,
+                           c1, c2, c3, m1, m2);
+        IGAFD_HIP_CHECK(hipGetLastError());
+      }
+  return IGAFD_OK;
+}
+
 template <template <int, int> class F, typename... Args>
 igafd_status dispatch(int dim, int p, Args... args) {
   switch (dim * 10 + p) {
@@ -396,6 +509,10 @@ struct AssembleOp {
   static igafd_status run(igafd_ctx* c) { return launch_assemble<D, P>(c); }
 };
 template <int D, int P>
+struct FeatureOp {
+  static igafd_status run(igafd_ctx* c, double* acc) { return launch_features<D, P>(c, acc); }
+};
+template <int D, int P>
 struct LoadOp {
   static igafd_status run(igafd_ctx* c, int k, double* b) { return launch_load<D, P>(c, k, b); }
 };
@@ -403,7 +520,7 @@ struct LoadOp {
 }  // namespace
 
 igafd_status assemble_band(igafd_ctx* c) {
-  IGAFD_HIP_CHECK(hipMemsetAsync(c->band, 0, sizeof(double) * c->H * c->Np, c->stream));
+  IGAFD_HIP_CHECK(hipMemsetAsync(c->band, 0, sizeof(double) * c->H * c->Ns, c->stream));
   IGAFD_HIP_CHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
   igafd_status st = dispatch<AssembleOp>(c->dim, c->p, c);
   if (st != IGAFD_OK) return st;
@@ -429,7 +546,7 @@ igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b) {
 igafd_status diagonals(igafd_ctx* c, double* dA, double* dP) {
   const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
   if (dA) {  // plane 0 of the band is the diagonal
-    hipLaunchKernelGGL(k_copy_plane, dim3(blocks), dim3(kBlock), 0, c->stream, c->band, dA, c->N);
+    hipLaunchKernelGGL(k_copy_plane, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, dA, c->N);
     IGAFD_HIP_CHECK(hipGetLastError());
   }
   if (dP) {
@@ -439,6 +556,51 @@ igafd_status diagonals(igafd_ctx* c, double* dA, double* dP) {
     IGAFD_HIP_CHECK(hipGetLastError());
   }
   return IGAFD_OK;
+}
+
+igafd_status features(igafd_ctx* c, float* feat) {
+  double* acc = nullptr;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&acc, sizeof(double) * 8 * (size_t)c->N));
+  igafd_status st = IGAFD_OK;
+  if (hipMemsetAsync(acc, 0, sizeof(double) * 8 * (size_t)c->N, c->stream) != hipSuccess) st = IGAFD_ERR_HIP;
+  if (st == IGAFD_OK) st = dispatch<FeatureOp>(c->dim, c->p, c, acc);
+  if (st == IGAFD_OK) {
+    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_features_finish, dim3(blocks), dim3(kBlock), 0, c->stream, acc, feat, c->N, c->p);
+    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(acc);
+  if (st == IGAFD_ERR_HIP) set_error("feature kernels failed");
+  return st;
+}
+
+igafd_status scaling_targets(igafd_ctx* c, float* t) {
+  double* dP = nullptr;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&dP, sizeof(double) * (size_t)c->N));
+  igafd_status st = diagonals(c, nullptr, dP);
+  if (st == IGAFD_OK) {
+    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_log_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, dP, t, c->N);
+    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(dP);
+  return st;
+}
+
+igafd_status diag_ratio_scaling(igafd_ctx* c, double* S) {
+  double* dP = nullptr;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&dP, sizeof(double) * (size_t)c->N));
+  igafd_status st = diagonals(c, nullptr, dP);
+  if (st == IGAFD_OK) {
+    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_sqrt_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, dP, S, c->N);
+    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(dP);
+  return st;
 }
 
 }  // namespace igafd

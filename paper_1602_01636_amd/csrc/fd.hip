@@ -102,17 +102,28 @@ __device__ inline f4_t mfma<PBF16>(const short* a, const float* bf, const double
 // D[k][c] = sum_i Wm[k][i] X(i, c) for k in this block's row range and the
 // wave's 16 columns.  TRX: X(i, c) = X[c * n + i] and D -> Y[c * n + k];
 // otherwise X(i, c) = X[b * bstride + i * C + c] and D -> Y[b * bstride + k * C + c].
+//
+// Block order: the nblk row blocks of one 64-column group run on the same XCD
+// (blocks are dealt to the 8 XCDs round robin), so the input tile they share
+// is read into one L2.  Operands of UNR K-steps are loaded before their MFMAs.
 template <class Pr, int MT, bool TRX, typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout* __restrict__ Y,
                                                  const typename Pr::W* __restrict__ Wm, int npad, int n, int C,
-                                                 long long bstride, Epi ep) {
+                                                 long long bstride, int nblk, int ncolblk, Epi ep) {
   using acc_t = typename Pr::acc;
   constexpr int KS = Pr::KS, KPL = Pr::KPL;
+  constexpr int UNR = 4;
   if (ep.flag && *ep.flag) return;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int rb = slot % nblk, cb = (slot / nblk) * 8 + xcd;
+  if (cb >= ncolblk) {  // idle block of the XCD-rounded grid
+    if ((ep.flags & EPI_DOT) && threadIdx.x == 0) ep.partial[blockIdx.x] = 0.0;
+    return;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int c0 = (blockIdx.x * (kBlock / 64) + wave) * 16;
-  const int k0 = blockIdx.z * MT * 16;
+  const int c0 = (cb * (kBlock / 64) + wave) * 16;
+  const int k0 = rb * MT * 16;
   const long long boff = (long long)blockIdx.y * bstride;
   const int c = c0 + col;
   const bool cok = c < C;
@@ -122,29 +133,36 @@ __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout
   for (int t = 0; t < MT; ++t) accv[t] = acc_t{0, 0, 0, 0};
 
   if (c0 < C) {
-    for (int i0 = 0; i0 < n; i0 += KS) {
-      float bf[KPL];
-      double bd[KPL];
+    const typename Pr::W* wbase = Wm + (long long)(k0 + col) * npad + grp * KPL;
+    for (int i0 = 0; i0 < n; i0 += UNR * KS) {
+      float bf[UNR][KPL];
+      double bd[UNR][KPL];
+      typename Pr::W a[UNR][MT][KPL];
 #pragma unroll
-      for (int j = 0; j < KPL; ++j) {
-        const int i = i0 + grp * KPL + j;
-        double v = 0.0;
-        if (cok && i < n) {
-          const long long addr = TRX ? (long long)c * n + i : boff + (long long)i * C + c;
-          v = (double)X[addr];
-          if (ep.flags & EPI_PRESCALE) v *= ep.S[addr];
+      for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+          const int i = i0 + u * KS + grp * KPL + j;
+          double v = 0.0;
+          if (cok && i < n) {
+            const long long addr = TRX ? (long long)c * n + i : boff + (long long)i * C + c;
+            v = (double)X[addr];
+            if (ep.flags & EPI_PRESCALE) v *= ep.S[addr];
+          }
+          bd[u][j] = v;
+          bf[u][j] = (float)v;
         }
-        bd[j] = v;
-        bf[j] = (float)v;
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+          for (int j = 0; j < KPL; ++j)
+            // rows k0 + t*16 + col < npad and columns < npad: W is zero padded
+            a[u][t][j] = (i0 + u * KS < npad) ? wbase[(long long)t * 16 * npad + i0 + u * KS + j] : 0;
       }
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const typename Pr::W* wrow = Wm + (long long)(k0 + t * 16 + col) * npad + i0 + grp * KPL;
-        typename Pr::W a[KPL];
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
-        for (int j = 0; j < KPL; ++j) a[j] = wrow[j];
-        accv[t] = mfma<Pr>(a, bf, bd, accv[t]);
-      }
+        for (int t = 0; t < MT; ++t) accv[t] = mfma<Pr>(a[u][t], bf[u], bd[u], accv[t]);
     }
   }
 
@@ -170,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout
   }
   if (ep.flags & EPI_DOT) {
     const double s = block_sum(dot);
-    if (threadIdx.x == 0) ep.partial[blockIdx.x + (long long)gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+    if (threadIdx.x == 0) ep.partial[blockIdx.x] = s;
   }
 }
 
@@ -178,22 +196,31 @@ struct ModeShape {
   int nblk, mt;
 };
 
-ModeShape mode_shape(int n) {
+// mt_max: row tiles per wave (fewer -> more waves, less reuse of each input tile)
+ModeShape mode_shape(int n, int mt_max) {
   const int ntiles = (n + 15) / 16;
-  const int nblk = (ntiles + 7) / 8;
-  return {nblk, (ntiles + nblk - 1) / nblk};
+  int mt = mt_max < 1 ? 1 : (mt_max > 8 ? 8 : mt_max);
+  if (mt > ntiles) mt = ntiles;
+  const int nblk = (ntiles + mt - 1) / mt;
+  return {nblk, mt};
+}
+
+int grid_x(int C, int nblk) {
+  const int ncolblk = (C + 63) / 64;
+  return 8 * nblk * ((ncolblk + 7) / 8);
 }
 
 template <class Pr, bool TRX, typename Tin, typename Tout>
-igafd_status launch_mode(hipStream_t st, const Tin* X, Tout* Y, const typename Pr::W* Wm, int npad, int n, int C,
-                         int B, long long bstride, const Epi& ep) {
-  const ModeShape ms = mode_shape(n);
-  const dim3 grid((unsigned)((C + 63) / 64), (unsigned)B, (unsigned)ms.nblk);
+igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, const typename Pr::W* Wm, int npad, int n,
+                         int C, int B, long long bstride, const Epi& ep) {
+  const ModeShape ms = mode_shape(n, mt_max);
+  const int ncolblk = (C + 63) / 64;
+  const dim3 grid((unsigned)grid_x(C, ms.nblk), (unsigned)B, 1);
   switch (ms.mt) {
 #define IGAFD_MT(M)                                                                                    \
   case M:                                                                                              \
     hipLaunchKernelGGL((k_mode<Pr, M, TRX, Tin, Tout>), grid, dim3(kBlock), 0, st, X, Y, Wm, npad, n, C, \
-                       bstride, ep);                                                                   \
+                       bstride, ms.nblk, ncolblk, ep);                                                 \
     break;
     IGAFD_MT(1) IGAFD_MT(2) IGAFD_MT(3) IGAFD_MT(4) IGAFD_MT(5) IGAFD_MT(6) IGAFD_MT(7) IGAFD_MT(8)
 #undef IGAFD_MT
@@ -215,9 +242,9 @@ template <>
 const short* wmat<PBF16>(const DevDir& d, int which) { return reinterpret_cast<const short*>(d.Wbf[which]); }
 
 int dot_blocks_for(const igafd_ctx* c) {
-  const ModeShape ms = mode_shape(c->n[0]);
+  const ModeShape ms = mode_shape(c->n[0], c->fd_tiles);
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
-  return ((C + 63) / 64) * ms.nblk;
+  return grid_x(C, ms.nblk);
 }
 
 // T: intermediate type (double for FP64, float otherwise)
@@ -253,22 +280,22 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
     return stt;
   if (c->dim == 3) {
     // forward: direction 1 (fast axis), 2, 3 (+ eigenvalue scaling)
-    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2 * n3, 1, 0, e_in)));
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, n3,
+    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2 * n3, 1, 0, e_in)));
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, n3,
                                              (long long)n1 * n2, e0)));
     e_lam.lamK = d[2].lam;
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b1, b0, wmat<Pr>(d[2], 0), d[2].npad, n3, n1 * n2, 1, 0, e_lam)));
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b1, b0, wmat<Pr>(d[2], 0), d[2].npad, n3, n1 * n2, 1, 0, e_lam)));
     // backward: direction 3, 2, 1
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b0, b1, wmat<Pr>(d[2], 1), d[2].npad, n3, n1 * n2, 1, 0, e0)));
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b1, b0, wmat<Pr>(d[1], 1), d[1].npad, n2, n1, n3,
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b0, b1, wmat<Pr>(d[2], 1), d[2].npad, n3, n1 * n2, 1, 0, e0)));
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b1, b0, wmat<Pr>(d[1], 1), d[1].npad, n2, n1, n3,
                                              (long long)n1 * n2, e0)));
-    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
+    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
   } else {
-    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in)));
+    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in)));
     e_lam.lamK = d[1].lam;
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, 1, 0, e_lam)));
-    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, b1, b0, wmat<Pr>(d[1], 1), d[1].npad, n2, n1, 1, 0, e0)));
-    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2, 1, 0, e_out)));
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, 1, 0, e_lam)));
+    IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b1, b0, wmat<Pr>(d[1], 1), d[1].npad, n2, n1, 1, 0, e0)));
+    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2, 1, 0, e_out)));
   }
 #undef IGAFD_TRY
   return IGAFD_OK;
@@ -293,11 +320,19 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
   }
 }
 
+// Row padding of the U matrices: every row tile any tile count can address.
 int fd_npad(int n) {
-  const ModeShape ms = mode_shape(n);
-  int rows = ms.nblk * ms.mt * 16;
+  const int ntiles = (n + 15) / 16;
+  int rows = 0;
+  for (int mt = 1; mt <= 8; ++mt) {
+    const int m = mt > ntiles ? ntiles : mt;
+    const int r = ((ntiles + m - 1) / m) * m * 16;
+    if (r > rows) rows = r;
+  }
   if (rows < n) rows = n;
-  return (rows + 31) / 32 * 32;
+  return (rows + 63) / 64 * 64;
 }
+
+
 
 }  // namespace igafd

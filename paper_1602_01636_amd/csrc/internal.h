@@ -87,13 +87,20 @@ struct igafd_ctx {
   igafd::DevDir ddir[3];
   // symmetric band of A: plane h (0..H-1) holds the entries of offset
   // center+h of the (2p+1)^d stencil, row-indexed; lower entries are read
-  // from the mirrored plane at the column row.
+  // from the mirrored plane at the column row.  Plane h starts at band + h*Ns;
+  // row i is at offset halo + i; the halo rows are zero.
   double* band = nullptr;
   int H = 0;
-  long long Np = 0;
+  long long Ns = 0;
+  long long halo = 0;
   long long nnz = 0;
+  int spmv_rows = 2;                       // rows per thread of the A product
+  int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
   // workspace
-  double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *zold = nullptr;
+  double *r = nullptr, *z = nullptr, *q = nullptr, *zold = nullptr;
+  double* pv_pad = nullptr;                // search direction with the band's zero halo
+  double* pv = nullptr;                    // = pv_pad + halo
+  double* xpad = nullptr;                  // staging buffer with zero halo for caller vectors
   double* fdbuf[2] = {nullptr, nullptr};   // FD intermediates (double or float)
   double* scaling = nullptr;
   bool scaling_set = false;
@@ -110,8 +117,12 @@ namespace igafd {
 igafd_status assemble_band(igafd_ctx* c);
 igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b);
 igafd_status diagonals(igafd_ctx* c, double* dA, double* dP);
+igafd_status features(igafd_ctx* c, float* feat);
+igafd_status scaling_targets(igafd_ctx* c, float* t);
+igafd_status diag_ratio_scaling(igafd_ctx* c, double* S);
 // spmv.hip
-igafd_status spmv(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
+igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
+igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
 int spmv_blocks(const igafd_ctx* c);
 // fd.hip
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,

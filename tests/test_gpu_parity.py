@@ -95,7 +95,8 @@ def test_solve_matches_oracle(api, name, prob):
         assert abs(info["iters"] - info_or["iters"]) <= 1
         assert info["true_relres"] <= 1e-8
         assert rel(to_host(u), u_or) <= 1e-7
-        np.testing.assert_allclose(info["history"][: len(info_or["history"])][:5], info_or["history"][:5], rtol=1e-6)
+        np.testing.assert_allclose(info["history"][: len(info_or["history"])][:5], info_or["history"][:5],
+                                   rtol=1e-6, atol=1e-12)
 
 
 def test_identity_map_converges_in_one_iteration(api):

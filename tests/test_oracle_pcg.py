@@ -111,3 +111,71 @@ def test_pcg_zero_rhs_and_maxit():
     b = assembly.assemble_load(prob, synth.RHS_SINPROD)
     u, info = pcg.solve(prob, A, F, b, maxit=2)
     assert info["iters"] == 2 and not info["converged"]
+
+
+def test_mlp_gradient_matches_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(7)
+    theta = rng.standard_normal(mlp.NPARAM) * 0.3
+    feat = rng.standard_normal((40, mlp.NIN))
+    target = rng.standard_normal(40) * 0.2
+    mean, inv_std = np.zeros(8), np.ones(8)
+    L, g = mlp.loss_and_grad(theta, mean, inv_std, feat, target)
+    idx = rng.choice(mlp.NPARAM, 60, replace=False)
+    idx = np.concatenate([idx, [mlp.NPARAM - 1, 0, 512, 4700]])  # b3, W1, b1, w3 entries
+    h = 1e-6
+    for k in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[k] = h
+        Lp, _ = mlp.loss_and_grad(theta + e, mean, inv_std, feat, target)
+        Lm, _ = mlp.loss_and_grad(theta - e, mean, inv_std, feat, target)
+        assert abs((Lp - Lm) / (2 * h) - g[k]) <= 1e-7 + 1e-5 * abs(g[k])
+
+
+def test_features_identity_and_ring():
+    from scipy.interpolate import BSpline
+    from oracle import mlp
+    prob = synth.uniform_problem(3, [3, 4, 2], 2)
+    f = mlp.features(prob)
+    np.testing.assert_allclose(f, np.tile([1, 1, 1, 0, 0, 0, 1, 2], (f.shape[0], 1)), atol=1e-14)
+    # thick ring: G = diag(w, 1/w, w) with w = pi (1 + xi1) / 2 depends on xi1 only,
+    # so each average is a 1D B-spline-weighted average in direction 1
+    p = 2
+    kn = [synth.jittered_knots(4, p, 1), synth.uniform_knots(3, p), synth.uniform_knots(2, p)]
+    prob = synth.make_problem(3, p, kn, geometry={"kind": "ring"})
+    f = mlp.features(prob)
+    k1 = kn[0]
+    xs, ws = [], []
+    for i in range(len(k1) - 1):
+        if k1[i] < k1[i + 1]:
+            t, w = np.polynomial.legendre.leggauss(p + 1)
+            xs.append(k1[i] + (k1[i + 1] - k1[i]) * (t + 1) / 2)
+            ws.append(w * (k1[i + 1] - k1[i]) / 2)
+    x, w = np.concatenate(xs), np.concatenate(ws)
+    m = len(k1) - p - 1
+    B = np.stack([np.nan_to_num(BSpline(k1, np.eye(m)[i], p, extrapolate=False)(x)) for i in range(m)], 1)[:, 1:-1]
+    wr = np.pi * (1 + x) / 2
+    avg_w = (B * (w * wr)[:, None]).sum(0) / (B * w[:, None]).sum(0)
+    avg_iw = (B * (w / wr)[:, None]).sum(0) / (B * w[:, None]).sum(0)
+    n = [len(k) - p - 3 for k in kn]
+    F = f.reshape(n[2], n[1], n[0], 8)
+    np.testing.assert_allclose(F[..., 0], np.broadcast_to(avg_w, F[..., 0].shape), rtol=1e-13)
+    np.testing.assert_allclose(F[..., 1], np.broadcast_to(avg_iw, F[..., 1].shape), rtol=1e-13)
+    np.testing.assert_allclose(F[..., 3:6], 0.0, atol=1e-14)
+
+
+def test_scaling_targets_identity_zero_and_exact_ratio_helps():
+    from oracle import mlp
+    prob = synth.uniform_problem(2, 6, 2)
+    np.testing.assert_allclose(mlp.targets(prob), 0.0, atol=1e-13)
+    # on a warped domain with kappa the exact diagonal ratio S P^-1 S does not
+    # need more iterations than P
+    prob = synth.uniform_problem(3, 6, 2, geometry=synth.warped_geometry(3),
+                                 coefficient=synth.sincos_coefficient(0.5, 1, 1, 0.0, 0.0))
+    A = assembly.assemble_matrix(prob)
+    F = fd.setup(prob)
+    b = assembly.assemble_load(prob, synth.RHS_SINPROD)
+    S = np.exp(mlp.targets(prob, A))
+    _, i0 = pcg.solve(prob, A, F, b)
+    _, i1 = pcg.solve(prob, A, F, b, scaling=S)
+    assert i1["iters"] <= i0["iters"]
