@@ -302,6 +302,8 @@ igafd_status parse_geometry(const igafd_problem* pr, GeomDesc* g) {
   return IGAFD_OK;
 }
 
+unsigned vblocks(const igafd_ctx* c) { return (unsigned)((c->N + kBlock - 1) / kBlock); }
+
 igafd_status alloc_workspace(igafd_ctx* c) {
   const size_t vb = sizeof(double) * (size_t)c->N;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->r, vb));
@@ -316,7 +318,9 @@ igafd_status alloc_workspace(igafd_ctx* c) {
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->q, vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[0], vb));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[1], vb));
-  c->npartial = std::max(spmv_blocks(c), fd_dot_blocks(c));
+  // partial sums: one (or two) per block of every reduction kernel, for any
+  // kernel shape the autotuner may pick
+  c->npartial = std::max((int)vblocks(c), fd_dot_blocks_max(c));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->state, sizeof(SolverState)));
   IGAFD_HIP_CHECK(hipHostMalloc((void**)&c->hstate, sizeof(SolverState), hipHostMallocDefault));
@@ -326,9 +330,20 @@ igafd_status alloc_workspace(igafd_ctx* c) {
   return IGAFD_OK;
 }
 
-unsigned vblocks(const igafd_ctx* c) { return (unsigned)((c->N + kBlock - 1) / kBlock); }
+// every reduction writes at most npartial (x 2) block partials
+igafd_status check_partials(const igafd_ctx* c, long long blocks) {
+  if (blocks > c->npartial) {
+    set_error("internal: reduction grid larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
+  return IGAFD_OK;
+}
 
 igafd_status reduce(igafd_ctx* c, int count, int two, int which, double* hist) {
+  if (count > c->npartial) {
+    set_error("internal: reduction count larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, c->stream, c->partial, count, two, which, c->state, hist);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
@@ -368,6 +383,7 @@ igafd_status enqueue_iteration(igafd_ctx* c, double* x, int prec, const double* 
                                double*& zold, double* hist) {
   const unsigned vb = vblocks(c);
   const int* flag = &c->state->flag;
+  IGAFD_TRY(check_partials(c, (long long)vb));
   // q = A p, (p, q)
   IGAFD_TRY(spmv(c, c->pv, c->q, c->partial, flag));
   IGAFD_TRY(reduce(c, spmv_blocks(c), 0, RED_PQ, hist));
@@ -427,6 +443,7 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
     IGAFD_TRY(spmv_unpadded(c, x, c->q, nullptr, nullptr));
     y = c->q;
   }
+  IGAFD_TRY(check_partials(c, (long long)vb));
   hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, b, y, c->r, x, o->use_x0 ? 1 : 0, c->N, c->partial);
   IGAFD_HIP_CHECK(hipGetLastError());
   IGAFD_TRY(reduce(c, (int)vb, 1, RED_BB_RR, hist));

@@ -109,22 +109,26 @@ __device__ inline f4_t mfma<PBF16>(const short* a, const float* bf, const double
 template <class Pr, int MT, bool TRX, typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout* __restrict__ Y,
                                                  const typename Pr::W* __restrict__ Wm, int npad, int n, int C,
-                                                 long long bstride, int nblk, int ncolblk, Epi ep) {
+                                                 long long bstride, int nblk, int ncolblk, int ngroups, Epi ep) {
   using acc_t = typename Pr::acc;
   constexpr int KS = Pr::KS, KPL = Pr::KPL;
   constexpr int UNR = 4;
   if (ep.flag && *ep.flag) return;
+  // work item (batch b, column block cb, row block rb); the row blocks of one
+  // (b, cb) group share their input tile and go to the same XCD
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int rb = slot % nblk, cb = (slot / nblk) * 8 + xcd;
-  if (cb >= ncolblk) {  // idle block of the XCD-rounded grid
+  const int rb = slot % nblk, group = (slot / nblk) * 8 + xcd;
+  if (group >= ngroups) {  // idle block of the XCD-rounded grid
     if ((ep.flags & EPI_DOT) && threadIdx.x == 0) ep.partial[blockIdx.x] = 0.0;
     return;
   }
+  const int cb = group % ncolblk;
+  const long long bidx = group / ncolblk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int c0 = (cb * (kBlock / 64) + wave) * 16;
   const int k0 = rb * MT * 16;
-  const long long boff = (long long)blockIdx.y * bstride;
+  const long long boff = bidx * bstride;
   const int c = c0 + col;
   const bool cok = c < C;
 
@@ -205,9 +209,9 @@ ModeShape mode_shape(int n, int mt_max) {
   return {nblk, mt};
 }
 
-int grid_x(int C, int nblk) {
-  const int ncolblk = (C + 63) / 64;
-  return 8 * nblk * ((ncolblk + 7) / 8);
+int grid_x(int C, int B, int nblk) {
+  const int ngroups = B * ((C + 63) / 64);
+  return 8 * nblk * ((ngroups + 7) / 8);
 }
 
 template <class Pr, bool TRX, typename Tin, typename Tout>
@@ -215,12 +219,12 @@ igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, cons
                          int C, int B, long long bstride, const Epi& ep) {
   const ModeShape ms = mode_shape(n, mt_max);
   const int ncolblk = (C + 63) / 64;
-  const dim3 grid((unsigned)grid_x(C, ms.nblk), (unsigned)B, 1);
+  const dim3 grid((unsigned)grid_x(C, B, ms.nblk), 1, 1);
   switch (ms.mt) {
 #define IGAFD_MT(M)                                                                                    \
   case M:                                                                                              \
     hipLaunchKernelGGL((k_mode<Pr, M, TRX, Tin, Tout>), grid, dim3(kBlock), 0, st, X, Y, Wm, npad, n, C, \
-                       bstride, ms.nblk, ncolblk, ep);                                                 \
+                       bstride, ms.nblk, ncolblk, B * ncolblk, ep);                                    \
     break;
     IGAFD_MT(1) IGAFD_MT(2) IGAFD_MT(3) IGAFD_MT(4) IGAFD_MT(5) IGAFD_MT(6) IGAFD_MT(7) IGAFD_MT(8)
 #undef IGAFD_MT
@@ -244,7 +248,7 @@ const short* wmat<PBF16>(const DevDir& d, int which) { return reinterpret_cast<c
 int dot_blocks_for(const igafd_ctx* c) {
   const ModeShape ms = mode_shape(c->n[0], c->fd_tiles);
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
-  return grid_x(C, ms.nblk);
+  return grid_x(C, 1, ms.nblk);
 }
 
 // T: intermediate type (double for FP64, float otherwise)
@@ -269,6 +273,10 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
     e_out.S = S;
   }
   if (partial) {
+    if (dot_blocks_for(c) > c->npartial) {
+      set_error("internal: FD grid larger than the partial-sum buffer");
+      return IGAFD_ERR_ARG;
+    }
     e_out.flags |= EPI_DOT;
     e_out.rdot = r;
     e_out.partial = partial;
@@ -304,6 +312,16 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
 }  // namespace
 
 int fd_dot_blocks(const igafd_ctx* c) { return dot_blocks_for(c); }
+
+int fd_dot_blocks_max(const igafd_ctx* c) {
+  const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
+  int m = 0;
+  for (int t = 1; t <= 8; ++t) {
+    const int g = grid_x(C, 1, mode_shape(c->n[0], t).nblk);
+    if (g > m) m = g;
+  }
+  return m;
+}
 
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
                       const int* flag) {

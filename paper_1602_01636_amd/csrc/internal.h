@@ -128,5 +128,6 @@ int spmv_blocks(const igafd_ctx* c);
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                       double* partial_rz, const int* flag);
 int fd_dot_blocks(const igafd_ctx* c);
+int fd_dot_blocks_max(const igafd_ctx* c);
 int fd_npad(int n);
 }  // namespace igafd

@@ -91,6 +91,10 @@ template <int D, int P, int R>
 igafd_status launch(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag) {
   const long long rows = (c->N + R - 1) / R;
   const unsigned blocks = (unsigned)((rows + kBlock - 1) / kBlock);
+  if (partial && (long long)blocks > c->npartial) {
+    set_error("internal: A-product grid larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
   hipLaunchKernelGGL((k_spmv<D, P, R>), dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, c->Ns, xpad, y,
                      c->n[0], c->n[1], c->N, partial, flag);
   IGAFD_HIP_CHECK(hipGetLastError());

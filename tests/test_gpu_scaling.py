@@ -1,9 +1,12 @@
 """GPU parity of the learned-scaling pieces against the FP64 oracle:
 features and targets (FP64 device arithmetic stored in FP32 -> 1e-6
-relative), the BF16 network forward (weights, inputs and activations rounded
-to BF16, unit roundoff 3.9e-3 -> 3e-2 on t), gradients (2-norm per parameter
-block within 5e-2 of the FP64 gradient with the same BF16-rounded weights),
-training (the loss falls) and the gain of S P^-1 S over P."""
+relative); the BF16 network forward and gradients against the FP64 oracle
+whose matrix-product operands are rounded to BF16 exactly where the device
+rounds them, so only FP32 accumulation order (and an occasional one-ulp BF16
+flip after tanhf) differs (1e-3 relative per parameter block; the unrounded FP64 gradient is reported and within 0.1:
+BF16 operands in back-propagation lose up to a few percent to cancellation);
+training (the loss falls, bitwise reproducibly) and the gain of S P^-1 S
+over P."""
 import numpy as np
 import pytest
 
@@ -69,22 +72,25 @@ def test_forward_and_gradient_match_fp64(api):
     theta = params[:npar].astype(np.float64)
     mean, inv_std = params[npar:npar + 8].astype(np.float64), params[npar + 8:].astype(np.float64)
     np.testing.assert_allclose(mean, feat.mean(0), rtol=1e-5, atol=1e-6)
-    # the device multiplies BF16-rounded weights with BF16-rounded activations
-    parts = omlp.unpack(theta)
-    parts["W1"], parts["W2"] = bf16_round(parts["W1"]), bf16_round(parts["W2"])
-    tq = omlp.pack(parts)
-    t_ref, _ = omlp.forward(tq, mean, inv_std, feat)
+    # the device normalises in FP32 and feeds BF16-rounded operands to every
+    # matrix product; the oracle gets the same normalised inputs and rounding
+    fn = ((feat - params[npar:npar + 8]) * params[npar + 8:]).astype(np.float32).astype(np.float64)
+    zero, one = np.zeros(8), np.ones(8)
+    t_ref, _ = omlp.forward(theta, zero, one, fn, rnd=bf16_round)
     tout = torch.empty(n, dtype=torch.float32, device="cuda")
     api.igafd_mlp_forward(m, fd_, n, t=tout)
-    assert np.max(np.abs(to_host(tout) - t_ref)) <= 3e-2 * max(1.0, np.abs(t_ref).max())
-    L_ref, g_ref = omlp.loss_and_grad(tq, mean, inv_std, feat, target)
+    # FP32 accumulation order, tanhf vs tanh: an occasional one-ulp BF16 flip
+    assert np.max(np.abs(to_host(tout) - t_ref)) <= 1e-3 * max(1.0, np.abs(t_ref).max())
+    L_ref, g_ref = omlp.loss_and_grad(theta, zero, one, fn, target, rnd=bf16_round)
+    _, g_exact = omlp.loss_and_grad(theta, zero, one, fn, target)
     L, g = api.igafd_mlp_gradient(m, fd_, td, n)
-    assert abs(L - L_ref) <= 3e-2 * L_ref
+    assert abs(L - L_ref) <= 1e-3 * L_ref
     k = 0
     for name, shape in omlp.SIZES:
         size = int(np.prod(shape))
-        a, b = g[k:k + size].astype(np.float64), g_ref[k:k + size]
-        assert rel(a, b) < 5e-2, (name, rel(a, b))
+        a = g[k:k + size].astype(np.float64)
+        assert rel(a, g_ref[k:k + size]) < 1e-3, (name, rel(a, g_ref[k:k + size]))
+        assert rel(a, g_exact[k:k + size]) < 1e-1, (name, rel(a, g_exact[k:k + size]))
         k += size
     m.close()
 
