@@ -846,6 +846,7 @@ igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out)
   if (const char* e = std::getenv("IGAFD_SPMV_ROWS")) c->spmv_rows = std::atoi(e);
   if (const char* e = std::getenv("IGAFD_FD_TILES")) c->fd_tiles = std::atoi(e);
   if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
+  if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
   if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
   if ((s = assemble_band(c.get())) != IGAFD_OK) return s;

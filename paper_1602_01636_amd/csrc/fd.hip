@@ -236,6 +236,334 @@ igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, cons
   return IGAFD_OK;
 }
 
+// ------------------------------------------------------------------------
+// Fused 3D passes.  The mode products of different directions commute, so
+// the apply is done in three passes over the tensor instead of six:
+//   A  per i3 slice X (n2 x n1):  Y = V2 (X V1^T)       directions 1, 2 forward
+//   B  per group of columns c = (i2, i1) of the (n3 x n1 n2) view:
+//      Z = W3b ((W3f X) / (lam1 + lam2 + lam3))       direction 3 and the scaling
+//   C  as A with the backward matrices                directions 1, 2 backward
+// The intermediate of each pass stays in LDS; the small matrices are read
+// from L2; every input element is read once per pass and every output written
+// once, so a pass moves 2 N values instead of the 4 N of two separate
+// products.
+// ------------------------------------------------------------------------
+
+// Operand handling of the fused passes: loaders return values of type V
+// (double for FP64, float otherwise), converted once into the MFMA operand Op
+// of one lane (KPL consecutive contracted-index values).
+template <class Pr>
+struct Ops;
+template <>
+struct Ops<PF64> {
+  using V = double;
+  using Op = double;
+  static __device__ inline Op pack(const V* v) { return v[0]; }
+  static __device__ inline d4_t mma(Op a, Op b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Ops<PF32> {
+  using V = float;
+  using Op = float;
+  static __device__ inline Op pack(const V* v) { return v[0]; }
+  static __device__ inline f4_t mma(Op a, Op b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Ops<PBF16> {
+  using V = float;
+  using Op = s4_t;
+  static __device__ inline Op pack(const V* v) {
+    return s4_t{to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3])};
+  }
+  static __device__ inline f4_t mma(Op a, Op b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class Pr>
+__device__ inline int row_of(int grp, int r) {
+  return Pr::ROW_STRIDE4 ? grp + 4 * r : 4 * grp + r;
+}
+
+constexpr int kSliceCols = 48;  // output columns (k1) per slice block
+constexpr int kDir3Cols = 32;   // columns (i2, i1) per direction-3 block
+constexpr int kMaxTilesPerWave = 3;
+
+// K-steps whose operands are loaded together, double buffered: while the
+// MFMAs of one group run, the loads of the next group are in flight.
+template <class Pr>
+struct Pipe {
+  static constexpr int UNR = Pr::KPL == 1 ? 4 : 1;
+  static constexpr int STEP = UNR * Pr::KS;
+};
+
+// Two chained contractions D = A2 (A1 B1) over a 48- or 32-column group:
+// the generic body of the fused passes.  LoadA(k, tile, j) / LoadB(k, t, j)
+// return operand values; after step 1 the tile goes through LDS (and the
+// epilogue functor `mid` may rescale it); step 2 reads its B operand there.
+template <class Pr, int NT, typename Tmid, typename A1, typename B1, typename Mid, typename A2>
+__device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], int K1, int K2, int mtiles, int wave,
+                                int grp, int col, Tmid* sT, int ldc, A1 loadA1, B1 loadB1, Mid mid, A2 loadA2) {
+  using acc_t = typename Pr::acc;
+  using O = Ops<Pr>;
+  using V = typename O::V;
+  using Op = typename O::Op;
+  constexpr int KPL = Pr::KPL, KS = Pr::KS, UNR = Pipe<Pr>::UNR, STEP = Pipe<Pr>::STEP;
+  Op av[2][UNR][kMaxTilesPerWave], bv[2][UNR][NT];
+  auto load1 = [&](int k0, Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      V tmp[KPL];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) tmp[j] = loadB1(k0 + u * KS + grp * KPL + j, t);
+        b[u][t] = O::pack(tmp);
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxTilesPerWave; ++m) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j)
+          tmp[j] = (wave + 4 * m < mtiles) ? loadA1(k0 + u * KS + grp * KPL + j, wave + 4 * m) : V(0);
+        a[u][m] = O::pack(tmp);
+      }
+    }
+  };
+  auto load2 = [&](int k0, Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      V tmp[KPL];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) tmp[j] = (V)sT[(k0 + u * KS + grp * KPL + j) * ldc + t * 16 + col];
+        b[u][t] = O::pack(tmp);
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxTilesPerWave; ++m) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j)
+          tmp[j] = (wave + 4 * m < mtiles) ? loadA2(k0 + u * KS + grp * KPL + j, wave + 4 * m) : V(0);
+        a[u][m] = O::pack(tmp);
+      }
+    }
+  };
+  auto compute = [&](Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int m = 0; m < kMaxTilesPerWave; ++m)
+        if (wave + 4 * m < mtiles) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[m][t] = O::mma(a[u][m], b[u][t], acc[m][t]);
+        }
+  };
+#pragma unroll
+  for (int m = 0; m < kMaxTilesPerWave; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+  // step 1 (operands past K1 read as zero through the loaders)
+  load1(0, av[0], bv[0]);
+  for (int k0 = 0; k0 < K1; k0 += 2 * STEP) {
+    if (k0 + STEP < K1) load1(k0 + STEP, av[1], bv[1]);
+    compute(av[0], bv[0]);
+    if (k0 + 2 * STEP < K1) load1(k0 + 2 * STEP, av[0], bv[0]);
+    if (k0 + STEP < K1) compute(av[1], bv[1]);
+  }
+  // intermediate tile to LDS (rows past the problem hold zeros)
+#pragma unroll
+  for (int m = 0; m < kMaxTilesPerWave; ++m) {
+    const int mt = wave + 4 * m;
+    if (mt >= mtiles) break;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + row_of<Pr>(grp, r);
+        sT[row * ldc + t * 16 + col] = (Tmid)mid(row, t, (double)acc[m][t][r]);
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kMaxTilesPerWave; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
+  // step 2: K2 rows of the LDS tile (zero rows up to the padded tile height)
+  load2(0, av[0], bv[0]);
+  for (int k0 = 0; k0 < K2; k0 += 2 * STEP) {
+    if (k0 + STEP < K2) load2(k0 + STEP, av[1], bv[1]);
+    compute(av[0], bv[0]);
+    if (k0 + 2 * STEP < K2) load2(k0 + 2 * STEP, av[0], bv[0]);
+    if (k0 + STEP < K2) compute(av[1], bv[1]);
+  }
+}
+
+// Pass A / C: Out[i2][k1] = sum_j2 V2[i2][j2] sum_i1 X[j2][i1] V1[k1][i1] for
+// slice blockIdx.y and output columns k1 in [blockIdx.x * 48, +48).  X, Out:
+// slice-contiguous (n2 x n1); V1, V2 row-major, zero padded to npad1, npad2.
+template <class Pr, typename Tin, typename Tout, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
+                                                  const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
+                                                  int npad1, int npad2, Epi ep) {
+  using acc_t = typename Pr::acc;
+  using V = typename Ops<Pr>::V;
+  constexpr int NT = kSliceCols / 16, LDC = kSliceCols + 1;
+  if (ep.flag && *ep.flag) return;
+  extern __shared__ char smem_raw[];
+  Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int mtiles = (n2 + 15) / 16;
+  const int cb = blockIdx.x;
+  const long long sbase = (long long)blockIdx.y * n1 * n2;
+  const Tin* Xs = X + sbase;
+  acc_t acc[kMaxTilesPerWave][NT];
+  // step 1: A = X (rows j2, contracted i1), B = V1^T (contracted i1, columns k1)
+  auto loadA1 = [&](int i1, int mt) -> V {
+    const int j2 = mt * 16 + col;
+    if (j2 >= n2 || i1 >= n1) return V(0);
+    const long long addr = (long long)j2 * n1 + i1;
+    if (ep.flags & EPI_PRESCALE) return (V)((double)Xs[addr] * ep.S[sbase + addr]);
+    return (V)Xs[addr];
+  };
+  auto loadB1 = [&](int i1, int t) -> V {
+    const int k1 = cb * kSliceCols + t * 16 + col;
+    return (k1 < n1 && i1 < npad1) ? (V)V1[(long long)k1 * npad1 + i1] : V(0);
+  };
+  auto mid = [&](int, int, double v) { return v; };
+  // step 2: A = V2 (rows i2, contracted j2), B = the LDS tile
+  auto loadA2 = [&](int j2, int mt) -> V {
+    return j2 < npad2 ? (V)V2[(long long)(mt * 16 + col) * npad2 + j2] : V(0);
+  };
+  two_step<Pr, NT>(acc, n1, n2, mtiles, wave, grp, col, sT, LDC, loadA1, loadB1, mid, loadA2);
+  double dot = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxTilesPerWave; ++m) {
+    const int mt = wave + 4 * m;
+    if (mt >= mtiles) break;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i2 = mt * 16 + row_of<Pr>(grp, r);
+        const int k1 = cb * kSliceCols + t * 16 + col;
+        if (i2 < n2 && k1 < n1) {
+          const long long addr = sbase + (long long)i2 * n1 + k1;
+          double v = (double)acc[m][t][r];
+          if (ep.flags & EPI_POSTSCALE) v *= ep.S[addr];
+          Out[addr] = (Tout)v;
+          if (ep.flags & EPI_DOT) dot += ep.rdot[addr] * v;
+        }
+      }
+  }
+  if (ep.flags & EPI_DOT) {
+    const double sum = block_sum(dot);
+    if (threadIdx.x == 0) ep.partial[blockIdx.x + (long long)gridDim.x * blockIdx.y] = sum;
+  }
+}
+
+// Pass B: Out[i3][c] = sum_k3 Wb[i3][k3] (sum_j3 Wf[k3][j3] X[j3][c]) / lamsum(k3, c)
+// for the 32 columns c of block blockIdx.x (c = i2 n1 + i1, C = n1 n2).
+template <class Pr, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
+                                                 const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
+                                                 int npad3, Epi ep) {
+  using acc_t = typename Pr::acc;
+  using V = typename Ops<Pr>::V;
+  constexpr int NT = kDir3Cols / 16, LDC = kDir3Cols + 1;
+  if (ep.flag && *ep.flag) return;
+  extern __shared__ char smem_raw[];
+  Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int mtiles = (n3 + 15) / 16;
+  const int c0 = blockIdx.x * kDir3Cols;
+  acc_t acc[kMaxTilesPerWave][NT];
+  // step 1: A = Wf (rows k3, contracted j3), B = X (contracted j3, columns c)
+  auto loadA1 = [&](int j3, int mt) -> V {
+    return j3 < npad3 ? (V)Wf[(long long)(mt * 16 + col) * npad3 + j3] : V(0);
+  };
+  auto loadB1 = [&](int j3, int t) -> V {
+    const int c = c0 + t * 16 + col;
+    return (c < C && j3 < n3) ? (V)X[(long long)j3 * C + c] : V(0);
+  };
+  // scaling by the eigenvalue sums between the two contractions
+  auto mid = [&](int k3, int t, double v) -> double {
+    const int c = c0 + t * 16 + col;
+    return (k3 < n3 && c < C) ? v / (ep.lamK[k3] + ep.lam2[c / ep.n1] + ep.lam1[c % ep.n1]) : 0.0;
+  };
+  auto loadA2 = [&](int k3, int mt) -> V {
+    return k3 < npad3 ? (V)Wb[(long long)(mt * 16 + col) * npad3 + k3] : V(0);
+  };
+  two_step<Pr, NT>(acc, n3, n3, mtiles, wave, grp, col, sT, LDC, loadA1, loadB1, mid, loadA2);
+#pragma unroll
+  for (int m = 0; m < kMaxTilesPerWave; ++m) {
+    const int mt = wave + 4 * m;
+    if (mt >= mtiles) break;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i3 = mt * 16 + row_of<Pr>(grp, r);
+        const int c = c0 + t * 16 + col;
+        if (i3 < n3 && c < C) Out[(long long)i3 * C + c] = (Tmid)acc[m][t][r];
+      }
+  }
+}
+
+// the fused path needs each direction's row tiles to fit 4 waves x 3 tiles
+// and the LDS tile of a slice pass within 64 KB (n2 <= 160 in FP64)
+bool fused_ok(const igafd_ctx* c) {
+  return c->dim == 3 && c->n[0] <= 160 && c->n[1] <= 160 && c->n[2] <= 160;
+}
+
+int slice_blocks(const igafd_ctx* c) { return ((c->n[0] + kSliceCols - 1) / kSliceCols) * c->n[2]; }
+
+template <class Pr, typename T, typename Tw>
+igafd_status apply_fused(igafd_ctx* c, const Tw* const* Wf, const Tw* const* Wb, const double* r, double* s,
+                         const double* S, double* partial, const int* flag) {
+  const DevDir* d = c->ddir;
+  const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+  T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
+  T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
+  const hipStream_t st = c->stream;
+  Epi e_in{}, e_lam{}, e_out{};
+  e_in.flag = e_lam.flag = e_out.flag = flag;
+  if (S) {
+    e_in.flags |= EPI_PRESCALE;
+    e_in.S = S;
+    e_out.flags |= EPI_POSTSCALE;
+    e_out.S = S;
+  }
+  if (partial) {
+    if (slice_blocks(c) > c->npartial) {
+      set_error("internal: FD grid larger than the partial-sum buffer");
+      return IGAFD_ERR_ARG;
+    }
+    e_out.flags |= EPI_DOT;
+    e_out.rdot = r;
+    e_out.partial = partial;
+  }
+  e_lam.n1 = n1;
+  e_lam.lamK = d[2].lam;
+  e_lam.lam1 = d[0].lam;
+  e_lam.lam2 = d[1].lam;
+  const dim3 gs((unsigned)((n1 + kSliceCols - 1) / kSliceCols), (unsigned)n3);
+  const size_t lds_s = sizeof(T) * ((n2 + 15) / 16 * 16) * (kSliceCols + 1);
+  const size_t lds_3 = sizeof(T) * ((n3 + 15) / 16 * 16) * (kDir3Cols + 1);
+  const int C = n1 * n2;
+  hipLaunchKernelGGL((k_slice<Pr, double, T, Tw, T>), gs, dim3(kBlock), lds_s, st, r, b0, Wf[0], Wf[1], n1, n2,
+                     d[0].npad, d[1].npad, e_in);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_dir3<Pr, Tw, T>), dim3((unsigned)((C + kDir3Cols - 1) / kDir3Cols)), dim3(kBlock), lds_3, st,
+                     b0, b1, Wf[2], Wb[2], n3, C, d[2].npad, e_lam);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_slice<Pr, T, double, Tw, T>), gs, dim3(kBlock), lds_s, st, b1, s, Wb[0], Wb[1], n1, n2,
+                     d[0].npad, d[1].npad, e_out);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
 template <class Pr>
 const typename Pr::W* wmat(const DevDir& d, int which);
 template <>
@@ -311,11 +639,11 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
 
 }  // namespace
 
-int fd_dot_blocks(const igafd_ctx* c) { return dot_blocks_for(c); }
+int fd_dot_blocks(const igafd_ctx* c) { return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c); }
 
 int fd_dot_blocks_max(const igafd_ctx* c) {
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
-  int m = 0;
+  int m = slice_blocks(c);
   for (int t = 1; t <= 8; ++t) {
     const int g = grid_x(C, 1, mode_shape(c->n[0], t).nblk);
     if (g > m) m = g;
@@ -325,6 +653,25 @@ int fd_dot_blocks_max(const igafd_ctx* c) {
 
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
                       const int* flag) {
+  if (c->fd_fused && fused_ok(c)) {
+    const DevDir* d = c->ddir;
+    switch (prec) {
+      case IGAFD_FP64: {
+        const double* Wf[3] = {d[0].W64[0], d[1].W64[0], d[2].W64[0]};
+        const double* Wb[3] = {d[0].W64[1], d[1].W64[1], d[2].W64[1]};
+        return apply_fused<PF64, double, double>(c, Wf, Wb, r, s, S, partial, flag);
+      }
+      case IGAFD_FP32:
+      case IGAFD_BF16: {
+        const float* Wf[3] = {d[0].W32[0], d[1].W32[0], d[2].W32[0]};
+        const float* Wb[3] = {d[0].W32[1], d[1].W32[1], d[2].W32[1]};
+        return prec == IGAFD_FP32 ? apply_fused<PF32, float, float>(c, Wf, Wb, r, s, S, partial, flag)
+                                  : apply_fused<PBF16, float, float>(c, Wf, Wb, r, s, S, partial, flag);
+      }
+      default:
+        break;
+    }
+  }
   switch (prec) {
     case IGAFD_FP64:
       return apply<PF64, double>(c, r, s, S, partial, flag);

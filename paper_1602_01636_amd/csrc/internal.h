@@ -96,6 +96,7 @@ struct igafd_ctx {
   long long nnz = 0;
   int spmv_rows = 2;                       // rows per thread of the A product
   int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
+  int fd_fused = 1;                        // 3D: three fused passes instead of six products
   // workspace
   double *r = nullptr, *z = nullptr, *q = nullptr, *zold = nullptr;
   double* pv_pad = nullptr;                // search direction with the band's zero halo
