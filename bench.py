@@ -1,6 +1,6 @@
 """Benchmark: PCG time-to-solve at 1e-8 relative residual on one MI355X.
 
-Workload (the 3D case the metric is quoted on): thick quarter ring
+Default workload (the 3D case the metric is quoted on): thick quarter ring
 F(xi) = ((1+xi1) cos(pi xi2/2), (1+xi1) sin(pi xi2/2), xi3), p = 3, 128^3
 elements (n = 129 per direction, N = 2,146,689 dofs), f = 3 pi^2 prod sin(pi x_i),
 x0 = 0, stop at ||r|| <= 1e-8 ||b||, FD preconditioner in FP64.
@@ -11,7 +11,15 @@ solves, preconditioner applies per second, per-kernel timings from HIP events
 on the library's stream, the roofline of the dominant kernel (the banded A
 product) and the FP64 oracle timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Other workloads (--workload), each printing one JSON line of the same form:
+  warped   unit cube warped by 8 seeded sine modes, kappa = 1 + 0.5 sin(2 pi x) cos(2 pi y),
+           p = 5, 96^3 elements; BF16 FD inside flexible PCG (FP64 and FP32 reported beside it)
+  batch    64 uneven problems (m_d ~ U{32..96}, p ~ U{2..5}, ring or warped), one batched call
+  learned  learned diagonal scaling: trained on 2000 small warped cubes, evaluated on the
+           p = 4, 112^3 warped cube: plain P, learned S P^-1 S, exact diagonal-ratio S
+  square   2D unit square, identity map, p = 3, 64^2 elements (one iteration: launch latency)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -28,6 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 FP64_PEAK_TF = 78.6
+FP32_PEAK_TF = 157.3
+BF16_PEAK_TF = 2500.0
+METRIC = "PCG time-to-solve @1e-8 rel. residual (s) + iters; precond applies/sec"
 
 
 def log(msg):
@@ -46,6 +57,83 @@ def event_time(torch, fn, reps):
     e.record()
     torch.cuda.synchronize()
     return s.elapsed_time(e) / reps
+
+
+def spmv_bytes(ctx):
+    """Algorithmic bytes of one A product: each stored (symmetric) value once,
+    x read once, y written once."""
+    return 8 * ((ctx.nnz + ctx.N) // 2) + 16 * ctx.N
+
+
+def fd_flops(ctx):
+    return 4 * ctx.N * sum(ctx.n[:ctx.dim]) + ctx.N
+
+
+def kernel_report(api, torch, ctx, reps=50, precisions=("fp64", "fp32", "bf16")):
+    """Event-timed A product and FD applies of one context."""
+    x = torch.randn(ctx.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), reps)
+    t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, x, y), reps) for pr in precisions}
+    by = spmv_bytes(ctx)
+    gbs = by / (t_spmv * 1e-3) / 1e9
+    fl = fd_flops(ctx)
+    log(f"spmv {t_spmv * 1e3:.1f} us = {gbs:.0f} GB/s; FD " +
+        " ".join(f"{pr} {t * 1e3:.1f} us" for pr, t in t_fd.items()))
+    return {"t_spmv": t_spmv, "t_fd": t_fd, "bytes": by, "gbs": gbs, "fd_flops": fl}
+
+
+def profiled_traffic(workload_tag):
+    """HBM/fabric bytes per A-product launch from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy),
+    used only while the A-product source is the one that was measured."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1602_01636_amd", "csrc", "spmv.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        fields = {}
+        for line in open(path):
+            key, _, val = line.strip().partition(": ")
+            if key.startswith("traffic_"):
+                fields[key] = val.strip()
+        if (fields.get("traffic_kernel") == "k_spmv" and fields.get("traffic_workload") == workload_tag
+                and fields.get("traffic_source_sha256_16") == sha):
+            return int(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
+def roofline(kr, workload_tag=None):
+    traffic, source = profiled_traffic(workload_tag) if workload_tag else (None, None)
+    out = {"bound": "hbm", "achieved": kr["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": kr["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_spmv (A x)",
+           "algorithmic_bytes": kr["bytes"]}
+    if traffic:
+        out["traffic_source"] = source
+        out["traffic_over_algorithmic"] = traffic / kr["bytes"]
+    return out
+
+
+def fd_roofline(kr, prec="fp64"):
+    peak = {"fp64": FP64_PEAK_TF, "fp32": FP32_PEAK_TF, "bf16": BF16_PEAK_TF}[prec]
+    tf = kr["fd_flops"] / kr["t_fd"][prec] / 1e9
+    return {"bound": "mfma", "precision": prec, "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak}
+
+
+def timed_solves(api, torch, ctx, b, u, steps, warmup, **kw):
+    for _ in range(warmup):
+        api.igafd_solve(ctx, b, u, rtol=1e-8, **kw)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = api.igafd_solve(ctx, b, u, rtol=1e-8, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        infos.append(info)
+        log(f"step {k}: {times[-1] * 1e3:.3f} ms iters {info['iters']} true_relres {info['true_relres']:.2e}")
+    return times, infos
 
 
 def cpu_baseline(target_iters, n_full, p, nnz_full):
@@ -88,15 +176,230 @@ def cpu_baseline(target_iters, n_full, p, nnz_full):
             "sample_s_per_iter": per_iter}
 
 
+def result(args, value, ms_per_step, dtype, workload, extra):
+    out = {"metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": workload}
+    out.update(extra)
+    return out
+
+
+def copy_calibration(torch):
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 1 GiB read + 1 GiB written")
+
+
+def rhs(api, torch, synth, ctx):
+    b = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
+    api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
+    return b
+
+
+def run_ring(args, api, torch, synth):
+    E, p = args.elements or 128, args.degree or 3
+    prob = synth.thick_ring(E=E, p=p)
+    t0 = time.perf_counter()
+    ctx = api.igafd_setup(prob)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    N, n = ctx.N, ctx.n[0]
+    log(f"setup {t_setup:.2f}s N={N} nnz={ctx.nnz} band={ctx.band_bytes / 1e9:.2f} GB")
+    b = rhs(api, torch, synth, ctx)
+    u = torch.zeros_like(b)
+    t_all = time.perf_counter()
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup)
+    wall = time.perf_counter() - t_all
+    u64 = u.clone()
+    ms_per_step = 1e3 * sum(times) / len(times)
+    iters = infos[-1]["iters"]
+    kr = kernel_report(api, torch, ctx)
+    variants = {}
+    if not args.no_variants:
+        for prec in ("fp32", "bf16"):
+            ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision=prec)
+            err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
+            variants[prec] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"],
+                              "true_relres": inf[-1]["true_relres"], "rel_err_vs_fp64": err}
+            log(f"{prec}: {variants[prec]}")
+    if args.copy_calibration:
+        copy_calibration(torch)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(iters, n, p, ctx.nnz)
+        log(f"cpu baseline {cpu['value']:.2f} s ({cpu['sample']})")
+    workload = {"workload": f"thick quarter ring, p={p}, {E}^3 elements, n={n}/dir, N={N} dofs, "
+                            f"f=3pi^2 prod sin(pi x_i), FP64 FD-preconditioned CG, rtol 1e-8",
+                "elements": E, "degree": p, "N": N, "nnz": ctx.nnz}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": iters, "true_relres": infos[-1]["true_relres"],
+        "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
+        "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
+        "variants": variants, "setup_s": t_setup, "wall_s_timed": wall,
+        "roofline": roofline(kr, f"thick_ring E={E} p={p}"), "fd_roofline": fd_roofline(kr),
+        "cpu_baseline": cpu})
+    ctx.close()
+    return out
+
+
+def run_warped(args, api, torch, synth):
+    E, p = args.elements or 96, args.degree or 5
+    prob = synth.warped_cube(E=E, p=p, seed=3)
+    t0 = time.perf_counter()
+    ctx = api.igafd_setup(prob)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"setup {t_setup:.2f}s N={ctx.N} nnz={ctx.nnz} band={ctx.band_bytes / 1e9:.2f} GB")
+    b = rhs(api, torch, synth, ctx)
+    u = torch.zeros_like(b)
+    ts64, inf64 = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1)
+    u64 = u.clone()
+    variants = {"fp64": {"s": float(np.median(ts64)), "iters": inf64[-1]["iters"],
+                         "true_relres": inf64[-1]["true_relres"]}}
+    ts32, inf32 = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision="fp32")
+    variants["fp32"] = {"s": float(np.median(ts32)), "iters": inf32[-1]["iters"],
+                        "true_relres": inf32[-1]["true_relres"],
+                        "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup, precision="bf16")
+    err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
+    ms_per_step = 1e3 * sum(times) / len(times)
+    kr = kernel_report(api, torch, ctx)
+    workload = {"workload": f"warped unit cube (8 sine modes, seed 3), kappa=1+0.5 sin(2pi x)cos(2pi y), p={p}, "
+                            f"{E}^3 elements, N={ctx.N} dofs, BF16 FD in flexible PCG, rtol 1e-8",
+                "elements": E, "degree": p, "N": ctx.N, "nnz": ctx.nnz}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64 (FD mode products bf16, fp32 accumulation)", workload, {
+        "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"], "rel_err_vs_fp64": err,
+        "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
+        "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
+        "variants": variants, "setup_s": t_setup, "roofline": roofline(kr), "fd_roofline": fd_roofline(kr, "bf16"),
+        "cpu_baseline": None})
+    ctx.close()
+    return out
+
+
+def run_batch(args, api, torch, synth):
+    probs = synth.batch_problems(seed=4)
+    t0 = time.perf_counter()
+    ctxs = [api.igafd_setup(pr) for pr in probs]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for c in ctxs:
+        api.igafd_autotune(c)
+    t_tune = time.perf_counter() - t0
+    bs = [rhs(api, torch, synth, c) for c in ctxs]
+    us = [torch.zeros_like(b) for b in bs]
+    band = sum(c.band_bytes for c in ctxs)
+    log(f"setup {t_setup:.2f}s autotune {t_tune:.2f}s, {len(ctxs)} problems, band {band / 1e9:.1f} GB")
+    for _ in range(args.warmup):
+        api.igafd_solve_batched(ctxs, bs, us)
+    walls, infos = [], None
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        infos, wall_ms = api.igafd_solve_batched(ctxs, bs, us)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t1)
+        log(f"step {k}: {walls[-1] * 1e3:.2f} ms (library wall {wall_ms:.2f} ms)")
+    assert all(i["status"] == "OK" and i["true_relres"] <= 1e-8 for i in infos)
+    iters = [i["iters"] for i in infos]
+    alg = sum((it + 2) * spmv_bytes(c) for it, c in zip(iters, ctxs))
+    ms_per_step = 1e3 * sum(walls) / len(walls)
+    # one-at-a-time solves of the same problems, for comparison
+    t1 = time.perf_counter()
+    for c, b, u in zip(ctxs, bs, us):
+        api.igafd_solve(c, b, u)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    big = max(range(len(ctxs)), key=lambda k: ctxs[k].band_bytes)
+    kr = kernel_report(api, torch, ctxs[big], precisions=("fp64",))
+    workload = {"workload": "64 uneven 3D problems (seed 4): m_d ~ U{32..96} per direction, p ~ U{2..5}, "
+                            "thick ring or warped cube, FP64 FD PCG, rtol 1e-8, one batched call",
+                "count": len(ctxs), "N_total": sum(c.N for c in ctxs), "band_GB": band / 1e9}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": iters, "sequential_s": t_seq, "spmv_equiv_GBps": alg / (ms_per_step * 1e-3) / 1e9,
+        "setup_s": t_setup, "autotune_s": t_tune,
+        "roofline": dict(roofline(kr), note=f"largest problem of the batch (#{big})"), "cpu_baseline": None})
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def run_learned(args, api, torch, synth):
+    from paper_1602_01636_amd import scaling
+    t0 = time.perf_counter()
+    mlp, hist, total = scaling.train_default(n_train=args.train, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained on {total} dofs of {args.train} problems in {t_train:.1f}s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    E, p = args.elements or 112, args.degree or 4
+    prob = synth.learned_eval_problem(E=E, p=p)
+    ctx = api.igafd_setup(prob)
+    b = rhs(api, torch, synth, ctx)
+    u = torch.zeros_like(b)
+    res = {}
+    ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1)
+    res["plain"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"]}
+    t1 = time.perf_counter()
+    scaling.predict_scaling(mlp, ctx)
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - t1
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup, use_scaling=True)
+    res["learned"] = {"s": float(np.median(times)), "iters": infos[-1]["iters"],
+                      "true_relres": infos[-1]["true_relres"], "fallback": infos[-1]["fallback"],
+                      "predict_s": t_pred}
+    api.igafd_set_scaling_diag_ratio(ctx)
+    ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, use_scaling=True)
+    res["exact_ratio"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"]}
+    log(f"plain {res['plain']['iters']} learned {res['learned']['iters']} exact {res['exact_ratio']['iters']}")
+    kr = kernel_report(api, torch, ctx, precisions=("fp64",))
+    ms_per_step = 1e3 * sum(times) / len(times)
+    workload = {"workload": f"warped unit cube (seed 10000), kappa=1+0.5 sin(2pi x)cos(2pi y), p={p}, {E}^3 elements, "
+                            f"N={ctx.N}, FP64 PCG with learned S P^-1 S (network trained on {args.train} small "
+                            f"warped cubes)", "elements": E, "degree": p, "N": ctx.N}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64 (network bf16, fp32 accumulation)", workload, {
+        "iters": infos[-1]["iters"], "variants": res, "train_s": t_train, "train_dofs": total,
+        "loss_first_last": [hist[0], hist[-1]], "roofline": roofline(kr), "cpu_baseline": None})
+    ctx.close()
+    mlp.close()
+    return out
+
+
+def run_square(args, api, torch, synth):
+    E, p = args.elements or 64, args.degree or 3
+    ctx = api.igafd_setup(synth.square_2d(E=E, p=p))
+    b = rhs(api, torch, synth, ctx)
+    u = torch.zeros_like(b)
+    times, infos = timed_solves(api, torch, ctx, b, u, max(args.steps, 20), args.warmup)
+    ms_per_step = 1e3 * float(np.median(times))
+    kr = kernel_report(api, torch, ctx, reps=200)
+    workload = {"workload": f"2D unit square, identity map, p={p}, {E}^2 elements, N={ctx.N}, FP64 FD PCG "
+                            f"(P = A: one iteration; launch-latency bound)", "elements": E, "degree": p, "N": ctx.N}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"],
+        "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
+        "roofline": roofline(kr), "cpu_baseline": None})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--elements", type=int, default=128)
-    ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square"])
+    ap.add_argument("--elements", type=int, default=0)
+    ap.add_argument("--degree", type=int, default=0)
+    ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single device and has no "
@@ -109,109 +412,9 @@ def main():
     import paper_1602_01636_amd as api
 
     torch.cuda.set_device(0)
-    E, p = args.elements, args.degree
-    prob = synth.thick_ring(E=E, p=p)
-    t0 = time.perf_counter()
-    ctx = api.igafd_setup(prob)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    N = ctx.N
-    n = ctx.n[0]
-    log(f"setup {t_setup:.2f}s N={N} nnz={ctx.nnz} band={ctx.band_bytes / 1e9:.2f} GB")
-    b = torch.zeros(N, dtype=torch.float64, device="cuda")
-    api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
-    u = torch.zeros_like(b)
-
-    def solve(prec="fp64"):
-        return api.igafd_solve(ctx, b, u, rtol=1e-8, precision=prec)
-
-    for _ in range(args.warmup):
-        solve()
-    torch.cuda.synchronize()
-    times, infos = [], []
-    t_all = time.perf_counter()
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        info = solve()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        infos.append(info)
-        log(f"step {k}: {times[-1] * 1e3:.2f} ms iters {info['iters']} true_relres {info['true_relres']:.2e}")
-    wall = time.perf_counter() - t_all
-    u64 = u.clone()
-    ms_per_step = 1e3 * sum(times) / len(times)
-    iters = infos[-1]["iters"]
-
-    # per-kernel device times (HIP events on the library stream)
-    x = torch.randn(N, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), 50)
-    t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, x, y), 50)
-            for pr in ("fp64", "fp32", "bf16")}
-    applies_per_s = {pr: 1e3 / t for pr, t in t_fd.items()}
-    # algorithmic bytes of one A product: each stored (symmetric) value once,
-    # x read once, y written once
-    unique_vals = (ctx.nnz + N) // 2
-    spmv_bytes = 8 * unique_vals + 16 * N
-    spmv_gbs = spmv_bytes / (t_spmv * 1e-3) / 1e9
-    fd_flops = 4 * N * 3 * n + N
-    log(f"spmv {t_spmv * 1e3:.1f} us = {spmv_gbs:.0f} GB/s; FD fp64 {t_fd['fp64'] * 1e3:.1f} us "
-        f"({fd_flops / t_fd['fp64'] / 1e9:.1f} TFLOP/s) fp32 {t_fd['fp32'] * 1e3:.1f} us bf16 {t_fd['bf16'] * 1e3:.1f} us")
-
-    variants = {}
-    if not args.no_variants:
-        for prec in ("fp32", "bf16"):
-            solve(prec)
-            ts = []
-            for _ in range(max(2, args.steps // 2)):
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                inf = solve(prec)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t1)
-            err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
-            variants[prec] = {"s": float(np.median(ts)), "iters": inf["iters"], "true_relres": inf["true_relres"],
-                              "rel_err_vs_fp64": err}
-            log(f"{prec}: {variants[prec]}")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(iters, n, p, ctx.nnz)
-        log(f"cpu baseline {cpu['value']:.2f} s ({cpu['sample']})")
-
-    out = {
-        "metric": "PCG time-to-solve @1e-8 rel. residual (s) + iters; precond applies/sec",
-        "value": ms_per_step / 1e3,
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": False,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"thick quarter ring, p={p}, {E}^3 elements, n={n}/dir, N={N} dofs, "
-                               f"f=3pi^2 prod sin(pi x_i), FP64 FD-preconditioned CG, rtol 1e-8",
-                   "elements": E, "degree": p, "N": N, "nnz": ctx.nnz},
-        "iters": iters,
-        "true_relres": infos[-1]["true_relres"],
-        "precond_applies_per_s": applies_per_s,
-        "kernel_ms": {"spmv": t_spmv, "fd_fp64": t_fd["fp64"], "fd_fp32": t_fd["fp32"], "fd_bf16": t_fd["bf16"]},
-        "variants": variants,
-        "setup_s": t_setup,
-        "wall_s_timed": wall,
-        "roofline": {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_spmv (A x)",
-                     "algorithmic_bytes": spmv_bytes},
-        "fd_roofline": {"bound": "mfma", "achieved": fd_flops / t_fd["fp64"] / 1e9, "peak": FP64_PEAK_TF,
-                        "unit": "TFLOP/s", "frac": fd_flops / t_fd["fp64"] / 1e9 / FP64_PEAK_TF},
-        "cpu_baseline": cpu,
-    }
-    ctx.close()
+    run = {"ring": run_ring, "warped": run_warped, "batch": run_batch, "learned": run_learned,
+           "square": run_square}[args.workload]
+    out = run(args, api, torch, synth)
     print(json.dumps(out), flush=True)
 
 

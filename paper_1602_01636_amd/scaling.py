@@ -20,7 +20,7 @@ def _dofs(problem):
     return int(np.prod([len(k) - p - 3 for k in problem["knots"]]))
 
 
-def build_dataset(problems, shuffle_seed=0):
+def build_dataset(problems, shuffle_seed=0, log=None):
     """Features (M x 8 float32) and targets (M float32) on the device, rows of
     all problems concatenated and then shuffled once."""
     import torch
@@ -29,11 +29,13 @@ def build_dataset(problems, shuffle_seed=0):
     feat = torch.empty(total * 8, dtype=torch.float32, device="cuda")
     targ = torch.empty(total, dtype=torch.float32, device="cuda")
     off = 0
-    for pr, n in zip(problems, sizes):
+    for k, (pr, n) in enumerate(zip(problems, sizes)):
         with B.igafd_setup(pr) as ctx:
             B.igafd_features(ctx, feat[off * 8:(off + n) * 8])
             B.igafd_scaling_targets(ctx, targ[off:off + n])
         off += n
+        if log and (k + 1) % 250 == 0:
+            log(f"dataset: {k + 1} of {len(problems)} problems")
     g = torch.Generator(device="cuda").manual_seed(shuffle_seed)
     perm = torch.randperm(total, device="cuda", generator=g)
     feat = feat.view(total, 8)[perm].contiguous().view(-1)
@@ -76,7 +78,7 @@ def predict_scaling(mlp, ctx):
 def train_default(n_train=2000, seed=0, epochs=20, log=None):
     """The standard training run: seeds 0..n_train-1 of synth.training_problem."""
     probs = [synth.training_problem(s) for s in range(n_train)]
-    feat, targ, total = build_dataset(probs, shuffle_seed=seed)
+    feat, targ, total = build_dataset(probs, shuffle_seed=seed, log=log)
     mlp = B.igafd_mlp_create(seed)
     hist = train(mlp, feat, targ, total, epochs=epochs, log=log)
     return mlp, hist, total
