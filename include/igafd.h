@@ -157,8 +157,11 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
                                  const igafd_solve_opts* opts, igafd_solve_info* infos, double* wall_ms);
 
 /* Kernel shape of one problem: fd_tiles (16-row tiles per wave in the mode
- * products, 1..8) and spmv_rows (rows per thread of the A product: 1, 2, 4).
- * Zero for both: time the candidates on this problem and keep the fastest. */
+ * products, 1..8) and spmv_rows (rows per thread of the row-parallel A
+ * product: 1, 2, 4; a nonzero value selects that kernel instead of the 3D
+ * tiled one).  Zero for both: time the candidates on this problem (row
+ * counts and tile shapes) and keep the fastest; may allocate the tile
+ * buffer, so call it at setup time, not inside a timed or captured region. */
 igafd_status igafd_autotune(igafd_ctx* ctx, int fd_tiles, int spmv_rows);
 
 /* Diagonals of A and P (N doubles each, device; either may be NULL). */

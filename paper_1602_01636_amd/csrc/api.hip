@@ -747,17 +747,37 @@ igafd_status autotune_impl(igafd_ctx* c, int reps) {
     }
   }
   c->fd_tiles = best_t;
-  best = 1e30f;
-  int best_r = c->spmv_rows;
-  for (int r : {1, 2, 4}) {
-    c->spmv_rows = r;
-    const float ms = time_it([&]() { (void)spmv(c, c->pv, c->q, nullptr, nullptr); });
-    if (ms < best) {
-      best = ms;
-      best_r = r;
+  // A product: the row-parallel kernel (1, 2, 4 rows per thread) and, in 3D,
+  // the tiled kernel with the best tile shape for 64, 80 and 160 KB of LDS
+  struct Cand {
+    int rows, b2, b3;
+  };
+  std::vector<Cand> cands = {{1, 0, 0}, {2, 0, 0}, {4, 0, 0}};
+  int dev = 0, maxlds = 0;
+  IGAFD_HIP_CHECK(hipGetDevice(&dev));
+  IGAFD_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  for (long long lim : {64LL * 1024, kTileLdsDefault, (long long)maxlds}) {
+    int b2 = 0, b3 = 0;
+    if (lim <= maxlds && spmv_pick_tile(c, lim, &b2, &b3)) {
+      bool seen = false;
+      for (const Cand& k : cands) seen = seen || (k.b2 == b2 && k.b3 == b3);
+      if (!seen) cands.push_back({c->spmv_rows, b2, b3});
     }
   }
-  c->spmv_rows = best_r;
+  best = 1e30f;
+  Cand best_c{c->spmv_rows, c->tile_b2, c->tile_b3};
+  for (const Cand& k : cands) {
+    c->spmv_rows = k.rows;
+    if (spmv_set_tile(c, k.b2, k.b3) != IGAFD_OK) continue;
+    bool ok = true;
+    const float ms = time_it([&]() { ok = ok && spmv(c, c->pv, c->q, nullptr, nullptr) == IGAFD_OK; });
+    if (ok && ms < best) {
+      best = ms;
+      best_c = k;
+    }
+  }
+  c->spmv_rows = best_c.rows;
+  IGAFD_TRY(spmv_set_tile(c, best_c.b2, best_c.b3));
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   IGAFD_HIP_CHECK(hipGetLastError());
@@ -792,6 +812,7 @@ void igafd_destroy(igafd_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (int l = 0; l < 3; ++l) free_dir(&c->ddir[l]);
   free_dev(c->band);
+  free_dev(c->ext);
   free_dev(c->r);
   free_dev(c->z);
   free_dev(c->zold);
@@ -849,6 +870,19 @@ igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out)
   if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
   if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
+  {
+    // 3D: tiled A product by default (IGAFD_SPMV_TILE=0 selects the row-parallel
+    // kernel, IGAFD_SPMV_TILE=<b2>x<b3> a tile shape)
+    int b2 = 0, b3 = 0;
+    const char* e = std::getenv("IGAFD_SPMV_TILE");
+    if (e && std::strchr(e, 'x')) {
+      b2 = std::atoi(e);
+      b3 = std::atoi(std::strchr(e, 'x') + 1);
+    } else if (!(e && std::atoi(e) == 0) && !spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
+      b2 = b3 = 0;
+    }
+    if ((s = spmv_set_tile(c.get(), b2, b3)) != IGAFD_OK) return s;
+  }
   if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
   *out = c.release();
@@ -973,7 +1007,10 @@ igafd_status igafd_autotune(igafd_ctx* c, int fd_tiles, int spmv_rows) {
       return IGAFD_ERR_ARG;
     }
     if (fd_tiles > 0) c->fd_tiles = fd_tiles;
-    if (spmv_rows > 0) c->spmv_rows = spmv_rows;
+    if (spmv_rows > 0) {
+      c->spmv_rows = spmv_rows;
+      return spmv_set_tile(c, 0, 0);  // an explicit row count selects the row-parallel kernel
+    }
     return IGAFD_OK;
   }
   return autotune_impl(c, 3);

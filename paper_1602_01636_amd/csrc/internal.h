@@ -14,6 +14,7 @@ namespace igafd {
 constexpr int kMaxDegree = 6;
 constexpr int kMaxModes = 16;
 constexpr int kBlock = 256;
+constexpr long long kTileLdsDefault = 80 * 1024;  // two tiled-product blocks per CU (160 KB LDS)
 
 void set_error(const std::string& msg);
 
@@ -94,7 +95,10 @@ struct igafd_ctx {
   long long Ns = 0;
   long long halo = 0;
   long long nnz = 0;
-  int spmv_rows = 2;                       // rows per thread of the A product
+  int spmv_rows = 2;                       // rows per thread of the row-parallel A product
+  int tile_b2 = 0, tile_b3 = 0;            // 3D tiled A product: lines per tile (0: row-parallel kernel)
+  double* ext = nullptr;                   // per-tile extended accumulators of the tiled product
+  long long ext_cap = 0;                   // doubles allocated at ext
   int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
   int fd_fused = 1;                        // 3D: three fused passes instead of six products
   // workspace
@@ -125,6 +129,8 @@ igafd_status diag_ratio_scaling(igafd_ctx* c, double* S);
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
 int spmv_blocks(const igafd_ctx* c);
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3);
+igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3);
 // fd.hip
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                       double* partial_rz, const int* flag);

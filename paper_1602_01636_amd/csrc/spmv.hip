@@ -87,6 +87,234 @@ __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
   if (i < N) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------------------
+// Tiled 3D product: every stored value read from HBM once.
+//
+// A block owns a tile of B2 x B3 grid lines (a line = the n1 rows of one
+// (i2, i3)); the B2 lines of one i3 form a run of contiguous rows, and each
+// lane takes two consecutive rows of a run (B2 n1 even), so every load moves
+// 16 bytes per lane.  For one line offset d = (o2, o3) of the upper stencil,
+// the lane at rows i, i+1 of line L computes
+//   gather   sum_o1 A(i, i+o) x[i+o]                   for its rows
+//   scatter  sum_o1 A(i-o1, i-o1+o) x[i-o1]            for the rows (L+d, t)
+// with o = o1 + o2 n1 + o3 n1 n2.  Both read stored upper values of rows of
+// the own run (the scatter ones o1 rows away, in the lines the gather just
+// fetched); values whose column leaves the grid are stored zeros, so rows
+// crossing a line end contribute exactly nothing.  The gather goes to
+// registers, the scatter to the LDS accumulator of the tile's extended region
+// (target lines i2 in [a0-p, a0+B2+p), i3 in [c0, c0+B3+p)): one add per row
+// and offset, each target slot written by one lane per offset, a barrier
+// between offsets, so every sum has a fixed order.  The accumulator goes to
+// a per-tile buffer; k_spmv_combine adds, for each row, the tiles covering it
+// in a fixed order (bitwise reproducible).
+// ------------------------------------------------------------------------
+constexpr int kTileMaxCh = 8;  // row pairs per thread (chunks of 256 pairs)
+// largest chunk count per degree that the compiler keeps in registers
+constexpr int kTileMaxChP[kMaxDegree + 1] = {0, 8, 8, 8, 4, 1, 1};
+
+// chunks of 256 row pairs of a B2 x B3 tile
+inline int tile_chunks(int b2, int b3, int n1) { return ((b2 * b3 * n1 + 1) / 2 + kBlock - 1) / kBlock; }
+
+typedef const __attribute__((address_space(1))) char* gbytes;  // global memory, byte addressed
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) d2_t __attribute__((aligned(8))) gd2;
+
+// 16 bytes at a uniform base plus a per-lane byte offset (32 bits: the tiled
+// path is used only when every row offset fits) plus a constant
+__device__ __forceinline__ d2_t ld2(gbytes base, unsigned off, int k) {
+  return *reinterpret_cast<gd2*>(base + off + 8 * k);
+}
+
+// a uniform global base the optimiser cannot relate across iterations
+__device__ __forceinline__ gbytes opaque(const double* p) {
+  unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  asm volatile("" : "+s"(v));
+  return reinterpret_cast<gbytes>(v);
+}
+
+// Values one lane loads for one chunk (rows i, i+1) and one line offset.
+template <int P>
+struct ChunkVals {
+  d2_t bg[2 * P + 1];  // A(i, i+o), A(i+1, i+1+o) per o1
+  d2_t bs[2 * P + 1];  // A(i-o1, i-o1+o), A(i+1-o1, i+1-o1+o) per o1
+  d2_t xg[P + 1];      // x[i+o2 n1+o3 n1n2 - p .. +1+p]
+  d2_t xs[P + 1];      // x[i-p .. i+1+p]
+};
+
+__device__ __forceinline__ double el(const d2_t* w, int k) { return (k & 1) ? w[k >> 1].y : w[k >> 1].x; }
+
+// One line offset (o2, o3); CENTER: o2 = o3 = 0 (o1 >= 0 stored; the
+// scatter lands on the own rows and stays in registers).  go[m]: byte
+// offset of the chunk's first row; tb[m]: its accumulator slot (rows of the
+// chunk whose bit in own is clear add to discard slots).  The chunks are
+// software pipelined: the loads of chunk m+1 are issued before the
+// arithmetic of chunk m.
+template <int P, int CH, bool CENTER>
+__device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restrict__ band, long long Ns,
+                                          const double* __restrict__ x, double* lds, int n1, long long n12, int E2,
+                                          int trash, unsigned own, const unsigned (&go)[CH], const int (&tb)[CH],
+                                          d2_t (&acc)[CH]) {
+  constexpr int W = 2 * P + 1;
+  constexpr int CTR = (W * W * W - 1) / 2;
+  constexpr int LO = CENTER ? 0 : -P;
+  const double* xg = x + (long long)o2 * n1 + (long long)o3 * n12;  // x shifted to the target line
+  const int shift = (o3 * E2 + o2) * n1;
+  const double* bp0 = band + (long long)(((o3 + P) * W + (o2 + P)) * W + P - CTR) * Ns;  // plane of o1 = 0
+  // Uniform bases, opaque to the optimiser: addresses stay "scalar base +
+  // lane offset" per line offset instead of per-lane pointer induction
+  // variables carried across offsets (one per chunk and o1, too many
+  // registers); the scatter's x window, the same for every offset, is
+  // reloaded (an L1 hit) rather than kept in registers.
+  const gbytes xsb = opaque(x), xgb = opaque(xg), bpb = opaque(bp0);
+  const long long plane = 8 * Ns;
+  auto load = [&](int m, ChunkVals<P>& v) {
+    const unsigned g = go[m];
+#pragma unroll
+    for (int o1 = LO; o1 <= P; ++o1) {
+      const gbytes pl = bpb + o1 * plane;
+      v.bg[o1 + P] = ld2(pl, g, 0);
+      if (!CENTER || o1 > 0) v.bs[o1 + P] = ld2(pl, g, -o1);
+    }
+#pragma unroll
+    for (int k = 0; k <= P; ++k) {
+      v.xg[k] = ld2(xgb, g, 2 * k - P);
+      v.xs[k] = ld2(xsb, g, 2 * k - P);
+    }
+  };
+  auto compute = [&](int m, const ChunkVals<P>& v) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int o1 = LO; o1 <= P; ++o1) {
+      acc[m].x = fma(v.bg[o1 + P].x, el(v.xg, o1 + P), acc[m].x);
+      acc[m].y = fma(v.bg[o1 + P].y, el(v.xg, o1 + P + 1), acc[m].y);
+      if (!CENTER || o1 > 0) {
+        s0 = fma(v.bs[o1 + P].x, el(v.xs, P - o1), s0);
+        s1 = fma(v.bs[o1 + P].y, el(v.xs, P - o1 + 1), s1);
+      }
+    }
+    if (CENTER) {
+      acc[m].x += s0;
+      acc[m].y += s1;
+    } else {
+      // no branch around the update (it would serialise the chunks' loads):
+      // rows without a slot add to their lane's discard slots
+      const int d = trash + 2 * (int)(threadIdx.x & 63);
+      const int i0 = (own & (1u << (2 * m))) ? tb[m] + shift : d;
+      const int i1 = (own & (2u << (2 * m))) ? tb[m] + shift + 1 : d + 1;
+      lds[i0] += s0;
+      lds[i1] += s1;
+    }
+  };
+  ChunkVals<P> v0, v1;
+  load(0, v0);
+#pragma unroll
+  for (int m = 0; m < CH; ++m) {
+    ChunkVals<P>& cur = (m & 1) ? v1 : v0;
+    ChunkVals<P>& nxt = (m & 1) ? v0 : v1;
+    if (m + 1 < CH) load(m + 1, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(m, cur);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// band, x: row 0 of plane 0 / of the zero-halo vector; ext: T2*T3 tiles of
+// E2*E3*n1 values (E2 = B2+2p, E3 = B3+p), line (e3, e2) = target line
+// (c0+e3, a0+e2-p).  LDS: the accumulator plus 128 discard slots.  Row pair
+// q = threadIdx.x + 256 m of the tile: rows 2q, 2q+1 of the concatenated runs.
+// The LDS tile allows about two blocks per CU: the occupancy target lets the
+// scheduler keep a chunk's loads in flight together.
+template <int P, int CH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile(
+    const double* __restrict__ band, long long Ns, const double* __restrict__ x, double* __restrict__ ext, int n1,
+    int n2, int n3, int B2, int B3, int T2, const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  extern __shared__ double lds[];
+  const int E2 = B2 + 2 * P, E3 = B3 + P;
+  const int elems = E2 * E3 * n1;
+  const int t2 = blockIdx.x % T2, t3 = blockIdx.x / T2;
+  const int a0 = t2 * B2, c0 = t3 * B3;
+  for (int k = threadIdx.x; k < elems; k += kBlock) lds[k] = 0.0;
+  const int run = B2 * n1;                                  // rows of one run (even)
+  const int valid_run = (n2 - a0 < B2 ? n2 - a0 : B2) * n1;  // rows of a run inside the grid
+  const long long n12 = (long long)n1 * n2;
+  unsigned go[CH];
+  int tb[CH];
+  d2_t acc[CH];
+  unsigned own = 0;  // bits 2m, 2m+1: rows of chunk m with an accumulator slot
+#pragma unroll
+  for (int m = 0; m < CH; ++m) {
+    const int r = 2 * (threadIdx.x + kBlock * m);  // first row of the pair in the tile
+    const int j = r / run, off = r - j * run;       // run (= b3) and row in the run
+    const bool ok0 = j < B3 && c0 + j < n3 && off < valid_run;
+    const bool ok1 = ok0 && off + 1 < valid_run;
+    go[m] = ok0 ? 8u * (unsigned)((long long)n1 * a0 + n12 * (c0 + j) + off) : 0u;
+    tb[m] = ok0 ? (j * E2 + P) * n1 + off : 0;
+    acc[m] = d2_t{0.0, 0.0};
+    own |= (ok0 ? 1u : 0u) << (2 * m);
+    own |= (ok1 ? 2u : 0u) << (2 * m);
+  }
+  const int trash = elems;
+  tile_pair<P, CH, true>(0, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+  __syncthreads();  // accumulator zeroed
+#pragma unroll 1
+  for (int o2 = 1; o2 <= P; ++o2) {
+    tile_pair<P, CH, false>(o2, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+    __syncthreads();
+  }
+#pragma unroll 1
+  for (int o3 = 1; o3 <= P; ++o3)
+#pragma unroll 1
+    for (int o2 = -P; o2 <= P; ++o2) {
+      tile_pair<P, CH, false>(o2, o3, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+      __syncthreads();
+    }
+  // own rows: no other lane writes them in this phase
+#pragma unroll
+  for (int m = 0; m < CH; ++m) {
+    if (own & (1u << (2 * m))) lds[tb[m]] += acc[m].x;
+    if (own & (2u << (2 * m))) lds[tb[m] + 1] += acc[m].y;
+  }
+  __syncthreads();
+  double* out = ext + (long long)blockIdx.x * elems;
+  for (int k = threadIdx.x; k < elems; k += kBlock) out[k] = lds[k];
+}
+
+__device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+
+// y[i] = sum over the tiles whose extended region holds row i (t3, then t2
+// ascending); optional per-block partial of (x, y).
+__global__ __launch_bounds__(kBlock) void k_spmv_combine(const double* __restrict__ ext,
+                                                         const double* __restrict__ x, double* __restrict__ y,
+                                                         int n1, int n2, int n3, int P, int B2, int B3, int T2,
+                                                         int T3, long long N, double* __restrict__ partial,
+                                                         const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (i < N) {
+    const int i1 = (int)(i % n1);
+    const long long rest = i / n1;
+    const int i2 = (int)(rest % n2), i3 = (int)(rest / n2);
+    const int E2 = B2 + 2 * P, E3 = B3 + P;
+    const long long elems = (long long)E2 * E3 * n1;
+    const int t3lo = max(0, ceil_div(i3 - E3 + 1, B3)), t3hi = min(T3 - 1, i3 / B3);
+    const int t2lo = max(0, ceil_div(i2 - B2 - P + 1, B2)), t2hi = min(T2 - 1, (i2 + P) / B2);
+    double s = 0.0;
+    for (int t3 = t3lo; t3 <= t3hi; ++t3)
+      for (int t2 = t2lo; t2 <= t2hi; ++t2) {
+        const int line = (i3 - t3 * B3) * E2 + (i2 - t2 * B2 + P);
+        s += ext[((long long)t3 * T2 + t2) * elems + (long long)line * n1 + i1];
+      }
+    y[i] = s;
+    dot = x[i] * s;
+  }
+  if (partial) {
+    const double sum = block_sum(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+  }
+}
+
 template <int D, int P, int R>
 igafd_status launch(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag) {
   const long long rows = (c->N + R - 1) / R;
@@ -113,16 +341,170 @@ igafd_status launch_r(igafd_ctx* c, const double* xpad, double* y, double* parti
   }
 }
 
+
+// Dynamic LDS above 64 KB needs the kernel attribute; set once when a tile
+// shape is selected (never inside a launch sequence that may be captured).
+template <int P>
+igafd_status tile_lds_attr(int ch, int lds) {
+  const void* fn = nullptr;
+  switch (ch) {
+#define IGAFD_CH(K)                              \
+  case K:                                        \
+    fn = (const void*)&k_spmv_tile<P, K>;        \
+    break;
+    IGAFD_CH(1) IGAFD_CH(2) IGAFD_CH(3) IGAFD_CH(4) IGAFD_CH(5) IGAFD_CH(6) IGAFD_CH(7) IGAFD_CH(8)
+#undef IGAFD_CH
+    default:
+      set_error("internal: bad tile chunk count");
+      return IGAFD_ERR_ARG;
+  }
+  IGAFD_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  return IGAFD_OK;
+}
+
+template <int P, int CH>
+igafd_status launch_tile_ch(igafd_ctx* c, const double* xpad, int T2, size_t lds, const int* flag) {
+  const int T3 = (c->n[2] + c->tile_b3 - 1) / c->tile_b3;
+  hipLaunchKernelGGL((k_spmv_tile<P, CH>), dim3((unsigned)(T2 * T3)), dim3(kBlock), lds, c->stream,
+                     c->band + c->halo, c->Ns, xpad, c->ext, c->n[0], c->n[1], c->n[2], c->tile_b2, c->tile_b3, T2,
+                     flag);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+template <int P>
+igafd_status launch_tile(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag) {
+  const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+  const int B2 = c->tile_b2, B3 = c->tile_b3;
+  const int T2 = (n2 + B2 - 1) / B2, T3 = (n3 + B3 - 1) / B3;
+  const int E2 = B2 + 2 * P, E3 = B3 + P;
+  const size_t lds = sizeof(double) * ((size_t)E2 * E3 * n1 + 2 * 64);
+  const int ch = tile_chunks(B2, B3, n1);
+  if ((long long)T2 * T3 * E2 * E3 * n1 > c->ext_cap || ch < 1 || ch > kTileMaxCh) {
+    set_error("internal: tile shape does not fit the tile buffer");
+    return IGAFD_ERR_ARG;
+  }
+  const unsigned vb = (unsigned)((c->N + kBlock - 1) / kBlock);
+  if (partial && (long long)vb > c->npartial) {
+    set_error("internal: A-product grid larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
+  igafd_status s = IGAFD_OK;
+  switch (ch) {
+#define IGAFD_CH(K)                                          \
+  case K:                                                    \
+    s = launch_tile_ch<P, K>(c, xpad, T2, lds, flag);        \
+    break;
+    IGAFD_CH(1) IGAFD_CH(2) IGAFD_CH(3) IGAFD_CH(4) IGAFD_CH(5) IGAFD_CH(6) IGAFD_CH(7) IGAFD_CH(8)
+#undef IGAFD_CH
+  }
+  if (s != IGAFD_OK) return s;
+  hipLaunchKernelGGL(k_spmv_combine, dim3(vb), dim3(kBlock), 0, c->stream, c->ext, xpad, y, n1, n2, n3, P, B2, B3,
+                     T2, T3, c->N, partial, flag);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
 }  // namespace
 
 int spmv_blocks(const igafd_ctx* c) {
+  if (c->tile_b2 > 0) return (int)((c->N + kBlock - 1) / kBlock);
   const int R = (c->spmv_rows == 1 || c->spmv_rows == 4) ? c->spmv_rows : 2;
   const long long rows = (c->N + R - 1) / R;
   return (int)((rows + kBlock - 1) / kBlock);
 }
 
+// Tile shape of the 3D tiled product: the most owned lines per extended
+// line (B2 B3 / ((B2+2p)(B3+p))) whose LDS accumulator fits `lds_limit`
+// bytes, with runs of an even number of rows (row pairs never straddle two
+// runs) and at most the per-degree number of chunks.
+// Returns false when no shape fits (or the problem is 2D or too large for
+// 32-bit row indices): the row-parallel kernel is used then.
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out) {
+  if (c->dim != 3 || c->N >= (1LL << 29)) return false;  // byte offsets of rows fit 32 bits
+  const int p = c->p, n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+  double best = 0.0;
+  for (int b3 = 1; b3 <= 16 && b3 <= n3; ++b3)
+    for (int b2 = 1; b2 <= 32 && b2 <= n2; ++b2) {
+      const int lines = b2 * b3;
+      if (lines < 2) continue;
+      if ((b2 * n1) % 2 != 0 || tile_chunks(b2, b3, n1) > kTileMaxChP[p]) continue;
+      const long long e = (long long)(b2 + 2 * p) * (b3 + p);
+      if (8 * (e * n1 + 128) > lds_limit) continue;
+      const double ratio = (double)lines / (double)e;
+      if (ratio > best * (1.0 + 1e-9)) {
+        best = ratio;
+        *b2_out = b2;
+        *b3_out = b3;
+      }
+    }
+  return best > 0.0;
+}
+
+// Select a tile shape (b2 = 0: the row-parallel kernel) and make the tile
+// buffer large enough (setup-time allocation only).
+igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3) {
+  if (b2 <= 0) {
+    c->tile_b2 = c->tile_b3 = 0;
+    return IGAFD_OK;
+  }
+  if (c->dim != 3 || b3 <= 0 || b2 > c->n[1] || b3 > c->n[2] || (b2 * c->n[0]) % 2 != 0 ||
+      tile_chunks(b2, b3, c->n[0]) > kTileMaxChP[c->p] || c->N >= (1LL << 29)) {
+    set_error("tile shape not usable for this problem");
+    return IGAFD_ERR_ARG;
+  }
+  const int p = c->p;
+  const long long T2 = (c->n[1] + b2 - 1) / b2, T3 = (c->n[2] + b3 - 1) / b3;
+  const long long need = T2 * T3 * (b2 + 2 * p) * (b3 + p) * (long long)c->n[0];
+  const long long lds = 8LL * ((b2 + 2 * p) * (b3 + p) * (long long)c->n[0] + 128);
+  int dev = 0, maxlds = 0;
+  IGAFD_HIP_CHECK(hipGetDevice(&dev));
+  IGAFD_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (lds > maxlds) {
+    set_error("tile accumulator larger than the device's LDS per block");
+    return IGAFD_ERR_ARG;
+  }
+  if (lds > 65536) {
+    const int ch = tile_chunks(b2, b3, c->n[0]);
+    igafd_status s = IGAFD_OK;
+    switch (p) {
+#define IGAFD_TCASE(P)                          \
+  case P:                                       \
+    s = tile_lds_attr<P>(ch, (int)lds);         \
+    break;
+      IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
+#undef IGAFD_TCASE
+      default:
+        set_error("unsupported degree");
+        return IGAFD_ERR_ARG;
+    }
+    if (s != IGAFD_OK) return s;
+  }
+  if (need > c->ext_cap) {
+    if (c->ext) IGAFD_HIP_CHECK(hipFree(c->ext));
+    c->ext = nullptr;
+    c->ext_cap = 0;
+    IGAFD_HIP_CHECK(hipMalloc((void**)&c->ext, sizeof(double) * (size_t)need));
+    c->ext_cap = need;
+  }
+  c->tile_b2 = b2;
+  c->tile_b3 = b3;
+  return IGAFD_OK;
+}
+
 // xpad: a vector with the zero halo of the band (row 0 at xpad[0]).
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag) {
+  if (c->tile_b2 > 0 && c->dim == 3) {
+    switch (c->p) {
+#define IGAFD_TCASE(P) \
+  case P:              \
+    return launch_tile<P>(c, xpad, y, partial, flag);
+      IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
+#undef IGAFD_TCASE
+      default:
+        break;
+    }
+  }
   switch (c->dim * 10 + c->p) {
 #define IGAFD_CASE(D, P) \
   case D * 10 + P:       \

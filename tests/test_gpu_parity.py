@@ -60,6 +60,34 @@ def test_apply_A_matches_oracle(api, name, prob, rng):
         np.testing.assert_allclose(to_host(dP), fd.diag_P(F), rtol=1e-12)
 
 
+TILE_CASES = [
+    # (problem, tile shape "b2xb3" or "0" for the row-parallel kernel)
+    ("3d_warped_kappa_p3", "4x1"), ("3d_warped_kappa_p3", "2x2"), ("3d_warped_kappa_p3", "4x4"),
+    ("3d_warped_kappa_p3", "0"), ("3d_ring_p2", "8x1"), ("3d_ring_p2", "2x6"), ("3d_identity_p1", "4x3"),
+    ("3d_warped_p5", "2x2"), ("3d_warped_p5", "0"), ("long_n1_p3", "4x4"), ("long_n1_p3", "0"),
+]
+
+
+def _tile_problem(name):
+    if name == "long_n1_p3":  # n1 = 129: 9 row chunks per lane, LDS tile above 64 KB
+        return synth.uniform_problem(3, [128, 6, 7], 3, geometry=synth.warped_geometry(8))
+    return dict(PROBLEMS)[name]
+
+
+@pytest.mark.parametrize("name,tile", TILE_CASES, ids=[f"{n}-{t}" for n, t in TILE_CASES])
+def test_apply_A_kernel_shapes(api, name, tile, rng, monkeypatch):
+    # every A-product kernel and tile shape against the oracle's assembled A
+    prob = _tile_problem(name)
+    A, _ = oracle_of(name, prob)
+    monkeypatch.setenv("IGAFD_SPMV_TILE", tile)
+    with api.igafd_setup(prob) as ctx:
+        x = rng.standard_normal(ctx.N)
+        y = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_A(ctx, to_dev(x), y)
+        scale = abs(A) @ np.abs(x)
+        assert np.max(np.abs(to_host(y) - A @ x) / scale) < 1e-12
+
+
 @pytest.mark.parametrize("name,prob", PROBLEMS, ids=IDS)
 def test_load_vector_matches_oracle(api, name, prob):
     with api.igafd_setup(prob) as ctx:
