@@ -16,6 +16,8 @@
 //
 // Optionally fuses the dot product (x, y) as one partial sum per block (fixed
 // reduction tree: deterministic).
+#include <algorithm>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -414,26 +416,39 @@ int spmv_blocks(const igafd_ctx* c) {
   return (int)((rows + kBlock - 1) / kBlock);
 }
 
-// Tile shape of the 3D tiled product: the most owned lines per extended
-// line (B2 B3 / ((B2+2p)(B3+p))) whose LDS accumulator fits `lds_limit`
-// bytes, with runs of an even number of rows (row pairs never straddle two
-// runs) and at most the per-degree number of chunks.
-// Returns false when no shape fits (or the problem is 2D or too large for
-// 32-bit row indices): the row-parallel kernel is used then.
+// Tile shape of the 3D tiled product, among those whose LDS accumulator fits
+// `lds_limit` bytes, whose runs hold an even number of rows (row pairs never
+// straddle two runs) and whose chunk count the compiler keeps in registers:
+// the best product of (owned lines / extended lines: stored values read per
+// accumulator value written), (row pairs / lanes of the chunks: lane use) and
+// (tiles / resident-block slots of the rounds the grid takes: tail of the
+// grid).  Returns false when no shape fits (or the problem is 2D or too large
+// for 32-bit row offsets): the row-parallel kernel is used then.
 bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out) {
   if (c->dim != 3 || c->N >= (1LL << 29)) return false;  // byte offsets of rows fit 32 bits
   const int p = c->p, n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+  int dev = 0, cus = 256, lds_cu = 160 * 1024;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  }
   double best = 0.0;
   for (int b3 = 1; b3 <= 16 && b3 <= n3; ++b3)
     for (int b2 = 1; b2 <= 32 && b2 <= n2; ++b2) {
       const int lines = b2 * b3;
       if (lines < 2) continue;
-      if ((b2 * n1) % 2 != 0 || tile_chunks(b2, b3, n1) > kTileMaxChP[p]) continue;
+      const int ch = tile_chunks(b2, b3, n1);
+      if ((b2 * n1) % 2 != 0 || ch > kTileMaxChP[p]) continue;
       const long long e = (long long)(b2 + 2 * p) * (b3 + p);
-      if (8 * (e * n1 + 128) > lds_limit) continue;
-      const double ratio = (double)lines / (double)e;
-      if (ratio > best * (1.0 + 1e-9)) {
-        best = ratio;
+      const long long lds = 8 * (e * n1 + 128);
+      if (lds > lds_limit) continue;
+      const long long tiles = (long long)((n2 + b2 - 1) / b2) * ((n3 + b3 - 1) / b3);
+      const long long slots = (long long)cus * std::max(1LL, (long long)lds_cu / lds);
+      const long long rounds = (tiles + slots - 1) / slots;
+      const double score = (double)lines / (double)e * ((double)lines * n1 / 2.0 / (ch * kBlock)) *
+                           ((double)tiles / (double)(rounds * slots));
+      if (score > best * (1.0 + 1e-9)) {
+        best = score;
         *b2_out = b2;
         *b3_out = b3;
       }
