@@ -249,36 +249,70 @@ igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, cons
 // products.
 // ------------------------------------------------------------------------
 
-// Operand handling of the fused passes: loaders return values of type V
-// (double for FP64, float otherwise), converted once into the MFMA operand Op
-// of one lane (KPL consecutive contracted-index values).
+// Operands of one 16-wide group of the contracted index for one lane: the
+// four consecutive indices k + 4g .. k + 4g + 3 (g = lane / 16), fetched with
+// 16- or 32-byte loads.  FP64 and FP32 feed value s of every lane to the s-th
+// of four 16x16x4 MFMAs (the same permutation of the contracted index on
+// both operands, so the sum is the same); BF16 packs the four values into
+// one 16x16x16 operand.
 template <class Pr>
-struct Ops;
+struct Grp;
 template <>
-struct Ops<PF64> {
+struct Grp<PF64> {
   using V = double;
-  using Op = double;
-  static __device__ inline Op pack(const V* v) { return v[0]; }
-  static __device__ inline d4_t mma(Op a, Op b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static constexpr int G = 1;  // groups per pipeline stage
 };
 template <>
-struct Ops<PF32> {
+struct Grp<PF32> {
   using V = float;
-  using Op = float;
-  static __device__ inline Op pack(const V* v) { return v[0]; }
-  static __device__ inline f4_t mma(Op a, Op b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static constexpr int G = 2;
 };
 template <>
-struct Ops<PBF16> {
+struct Grp<PBF16> {
   using V = float;
-  using Op = s4_t;
-  static __device__ inline Op pack(const V* v) {
-    return s4_t{to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3])};
-  }
-  static __device__ inline f4_t mma(Op a, Op b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-  }
+  static constexpr int G = 2;
 };
+
+typedef double d2u_t __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
+
+// four consecutive values (8-byte / 4-byte aligned), converted to V
+template <typename V>
+__device__ inline void ld4(const double* p, V (&o)[4]) {
+  const d2u_t u = *reinterpret_cast<const d2u_t*>(p), w = *reinterpret_cast<const d2u_t*>(p + 2);
+  o[0] = (V)u.x;
+  o[1] = (V)u.y;
+  o[2] = (V)w.x;
+  o[3] = (V)w.y;
+}
+template <typename V>
+__device__ inline void ld4(const float* p, V (&o)[4]) {
+  const f4u_t u = *reinterpret_cast<const f4u_t*>(p);
+  o[0] = (V)u.x;
+  o[1] = (V)u.y;
+  o[2] = (V)u.z;
+  o[3] = (V)u.w;
+}
+// the first `valid` of four values, zeros after
+template <typename T, typename V>
+__device__ inline void ld4_tail(const T* p, int valid, V (&o)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) o[j] = j < valid ? (V)p[j] : V(0);
+}
+
+template <class Pr>
+__device__ inline void grp_mma(const typename Grp<Pr>::V (&a)[4], const typename Grp<Pr>::V (&b)[4],
+                               typename Pr::acc& c);
+template <>
+__device__ inline void grp_mma<PF64>(const double (&a)[4], const double (&b)[4], d4_t& c) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+}
+template <>
+__device__ inline void grp_mma<PF32>(const float (&a)[4], const float (&b)[4], f4_t& c) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+}
 
 template <class Pr>
 __device__ inline int row_of(int grp, int r) {
@@ -289,90 +323,117 @@ constexpr int kSliceCols = 48;  // output columns (k1) per slice block
 constexpr int kDir3Cols = 32;   // columns (i2, i1) per direction-3 block
 constexpr int kMaxTilesPerWave = 3;
 
-// K-steps whose operands are loaded together, double buffered: while the
-// MFMAs of one group run, the loads of the next group are in flight.
-template <class Pr>
-struct Pipe {
-  static constexpr int UNR = Pr::KPL == 1 ? 4 : 1;
-  static constexpr int STEP = UNR * Pr::KS;
-};
+// row length of the transposed LDS tile (a multiple of 16 bytes)
+template <typename T>
+__host__ __device__ inline int lds_ld(int mtiles) {
+  return mtiles * 16 + 16 / (int)sizeof(T);
+}
 
 // Two chained contractions D = A2 (A1 B1) over a 48- or 32-column group:
-// the generic body of the fused passes.  LoadA(k, tile, j) / LoadB(k, t, j)
-// return operand values; after step 1 the tile goes through LDS (and the
-// epilogue functor `mid` may rescale it); step 2 reads its B operand there.
+// the generic body of the fused passes.  loadA1(k, tile, v[4]) /
+// loadB1(k, t, v[4]) fill the four values at contracted indices k..k+3 (k a
+// multiple of 4, k < K1 rounded up to 16; values past K1 must be zero on at
+// least one side).  The step-1 tile goes through LDS transposed (column c of
+// the block holds its rows contiguously, so step 2 reads 16-byte vectors),
+// rescaled on the way by `mid`.  Operand loads are double buffered: while the
+// MFMAs of one stage run, the loads of the next are in flight.
 template <class Pr, int NT, typename Tmid, typename A1, typename B1, typename Mid, typename A2>
 __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], int K1, int K2, int mtiles, int wave,
-                                int grp, int col, Tmid* sT, int ldc, A1 loadA1, B1 loadB1, Mid mid, A2 loadA2) {
+                                int grp, int col, Tmid* sT, int ldt, A1 loadA1, B1 loadB1, Mid mid, A2 loadA2) {
   using acc_t = typename Pr::acc;
-  using O = Ops<Pr>;
-  using V = typename O::V;
-  using Op = typename O::Op;
-  constexpr int KPL = Pr::KPL, KS = Pr::KS, UNR = Pipe<Pr>::UNR, STEP = Pipe<Pr>::STEP;
-  Op av[2][UNR][kMaxTilesPerWave], bv[2][UNR][NT];
-  auto load1 = [&](int k0, Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+  using V = typename Grp<Pr>::V;
+  constexpr int G = Grp<Pr>::G, STEP = 16 * G, MT = kMaxTilesPerWave;
+  V av[2][G][MT][4], bv[2][G][NT][4];
+  auto zero4 = [](V (&v)[4]) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      V tmp[KPL];
+    for (int j = 0; j < 4; ++j) v[j] = V(0);
+  };
+  auto load1 = [&](int k0, V (&a)[G][MT][4], V (&b)[G][NT][4]) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int k = k0 + 16 * u + 4 * grp;
+      const bool on = k0 + 16 * u < K1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int j = 0; j < KPL; ++j) tmp[j] = loadB1(k0 + u * KS + grp * KPL + j, t);
-        b[u][t] = O::pack(tmp);
+        if (on)
+          loadB1(k, t, b[u][t]);
+        else
+          zero4(b[u][t]);
       }
 #pragma unroll
-      for (int m = 0; m < kMaxTilesPerWave; ++m) {
-#pragma unroll
-        for (int j = 0; j < KPL; ++j)
-          tmp[j] = (wave + 4 * m < mtiles) ? loadA1(k0 + u * KS + grp * KPL + j, wave + 4 * m) : V(0);
-        a[u][m] = O::pack(tmp);
+      for (int m = 0; m < MT; ++m) {
+        if (on && wave + 4 * m < mtiles)
+          loadA1(k, wave + 4 * m, a[u][m]);
+        else
+          zero4(a[u][m]);
       }
     }
   };
-  auto load2 = [&](int k0, Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+  auto load2 = [&](int k0, V (&a)[G][MT][4], V (&b)[G][NT][4]) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      V tmp[KPL];
+    for (int u = 0; u < G; ++u) {
+      const int k = k0 + 16 * u + 4 * grp;
+      const bool on = k0 + 16 * u < K2;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int j = 0; j < KPL; ++j) tmp[j] = (V)sT[(k0 + u * KS + grp * KPL + j) * ldc + t * 16 + col];
-        b[u][t] = O::pack(tmp);
+        if (on)
+          ld4(sT + (t * 16 + col) * ldt + k, b[u][t]);
+        else
+          zero4(b[u][t]);
       }
 #pragma unroll
-      for (int m = 0; m < kMaxTilesPerWave; ++m) {
-#pragma unroll
-        for (int j = 0; j < KPL; ++j)
-          tmp[j] = (wave + 4 * m < mtiles) ? loadA2(k0 + u * KS + grp * KPL + j, wave + 4 * m) : V(0);
-        a[u][m] = O::pack(tmp);
+      for (int m = 0; m < MT; ++m) {
+        if (on && wave + 4 * m < mtiles)
+          loadA2(k, wave + 4 * m, a[u][m]);
+        else
+          zero4(a[u][m]);
       }
     }
   };
-  auto compute = [&](Op (&a)[UNR][kMaxTilesPerWave], Op (&b)[UNR][NT]) {
+  auto compute = [&](int k0, int K, V (&a)[G][MT][4], V (&b)[G][NT][4]) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u)
+    for (int u = 0; u < G; ++u) {
+      if (k0 + 16 * u >= K) break;
+      if constexpr (Pr::KPL == 1) {
 #pragma unroll
-      for (int m = 0; m < kMaxTilesPerWave; ++m)
-        if (wave + 4 * m < mtiles) {
+        for (int m = 0; m < MT; ++m)
+          if (wave + 4 * m < mtiles) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[m][t] = O::mma(a[u][m], b[u][t], acc[m][t]);
-        }
+            for (int t = 0; t < NT; ++t) grp_mma<Pr>(a[u][m], b[u][t], acc[m][t]);
+          }
+      } else {
+        s4_t pa[MT], pb[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          pa[m] = s4_t{to_bf16(a[u][m][0]), to_bf16(a[u][m][1]), to_bf16(a[u][m][2]), to_bf16(a[u][m][3])};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          pb[t] = s4_t{to_bf16(b[u][t][0]), to_bf16(b[u][t][1]), to_bf16(b[u][t][2]), to_bf16(b[u][t][3])};
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (wave + 4 * m < mtiles) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[m], pb[t], acc[m][t], 0, 0, 0);
+          }
+      }
+    }
   };
 #pragma unroll
-  for (int m = 0; m < kMaxTilesPerWave; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
-  // step 1 (operands past K1 read as zero through the loaders)
+  // step 1
   load1(0, av[0], bv[0]);
   for (int k0 = 0; k0 < K1; k0 += 2 * STEP) {
     if (k0 + STEP < K1) load1(k0 + STEP, av[1], bv[1]);
-    compute(av[0], bv[0]);
+    compute(k0, K1, av[0], bv[0]);
     if (k0 + 2 * STEP < K1) load1(k0 + 2 * STEP, av[0], bv[0]);
-    if (k0 + STEP < K1) compute(av[1], bv[1]);
+    if (k0 + STEP < K1) compute(k0 + STEP, K1, av[1], bv[1]);
   }
-  // intermediate tile to LDS (rows past the problem hold zeros)
+  // intermediate tile to LDS, transposed (rows past the problem hold zeros)
 #pragma unroll
-  for (int m = 0; m < kMaxTilesPerWave; ++m) {
+  for (int m = 0; m < MT; ++m) {
     const int mt = wave + 4 * m;
     if (mt >= mtiles) break;
 #pragma unroll
@@ -380,21 +441,21 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + row_of<Pr>(grp, r);
-        sT[row * ldc + t * 16 + col] = (Tmid)mid(row, t, (double)acc[m][t][r]);
+        sT[(t * 16 + col) * ldt + row] = (Tmid)mid(row, t, (double)acc[m][t][r]);
       }
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < kMaxTilesPerWave; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = acc_t{0, 0, 0, 0};
-  // step 2: K2 rows of the LDS tile (zero rows up to the padded tile height)
+  // step 2: K2 rows of the LDS tile
   load2(0, av[0], bv[0]);
   for (int k0 = 0; k0 < K2; k0 += 2 * STEP) {
     if (k0 + STEP < K2) load2(k0 + STEP, av[1], bv[1]);
-    compute(av[0], bv[0]);
+    compute(k0, K2, av[0], bv[0]);
     if (k0 + 2 * STEP < K2) load2(k0 + 2 * STEP, av[0], bv[0]);
-    if (k0 + STEP < K2) compute(av[1], bv[1]);
+    if (k0 + STEP < K2) compute(k0 + STEP, K2, av[1], bv[1]);
   }
 }
 
@@ -406,36 +467,55 @@ __global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tou
                                                   const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
                                                   int npad1, int npad2, Epi ep) {
   using acc_t = typename Pr::acc;
-  using V = typename Ops<Pr>::V;
-  constexpr int NT = kSliceCols / 16, LDC = kSliceCols + 1;
+  using V = typename Grp<Pr>::V;
+  constexpr int NT = kSliceCols / 16;
   if (ep.flag && *ep.flag) return;
   extern __shared__ char smem_raw[];
   Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int mtiles = (n2 + 15) / 16;
+  const int ldt = lds_ld<Tmid>(mtiles);
   const int cb = blockIdx.x;
   const long long sbase = (long long)blockIdx.y * n1 * n2;
   const Tin* Xs = X + sbase;
   acc_t acc[kMaxTilesPerWave][NT];
   // step 1: A = X (rows j2, contracted i1), B = V1^T (contracted i1, columns k1)
-  auto loadA1 = [&](int i1, int mt) -> V {
+  auto loadA1 = [&](int i1, int mt, V (&v)[4]) {
     const int j2 = mt * 16 + col;
-    if (j2 >= n2 || i1 >= n1) return V(0);
+    if (j2 >= n2) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = V(0);
+      return;
+    }
     const long long addr = (long long)j2 * n1 + i1;
-    if (ep.flags & EPI_PRESCALE) return (V)((double)Xs[addr] * ep.S[sbase + addr]);
-    return (V)Xs[addr];
+    if (i1 + 4 <= n1)
+      ld4(Xs + addr, v);
+    else
+      ld4_tail(Xs + addr, n1 - i1, v);
+    if (ep.flags & EPI_PRESCALE) {
+      V s[4];
+      if (i1 + 4 <= n1)
+        ld4(ep.S + sbase + addr, s);
+      else
+        ld4_tail(ep.S + sbase + addr, n1 - i1, s);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (V)((double)v[j] * (double)s[j]);
+    }
   };
-  auto loadB1 = [&](int i1, int t) -> V {
+  auto loadB1 = [&](int i1, int t, V (&v)[4]) {
     const int k1 = cb * kSliceCols + t * 16 + col;
-    return (k1 < n1 && i1 < npad1) ? (V)V1[(long long)k1 * npad1 + i1] : V(0);
+    if (k1 < n1) {
+      ld4(V1 + (long long)k1 * npad1 + i1, v);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = V(0);
+    }
   };
   auto mid = [&](int, int, double v) { return v; };
   // step 2: A = V2 (rows i2, contracted j2), B = the LDS tile
-  auto loadA2 = [&](int j2, int mt) -> V {
-    return j2 < npad2 ? (V)V2[(long long)(mt * 16 + col) * npad2 + j2] : V(0);
-  };
-  two_step<Pr, NT>(acc, n1, n2, mtiles, wave, grp, col, sT, LDC, loadA1, loadB1, mid, loadA2);
+  auto loadA2 = [&](int j2, int mt, V (&v)[4]) { ld4(V2 + (long long)(mt * 16 + col) * npad2 + j2, v); };
+  two_step<Pr, NT>(acc, n1, n2, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
   double dot = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
@@ -469,33 +549,31 @@ __global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmi
                                                  const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
                                                  int npad3, Epi ep) {
   using acc_t = typename Pr::acc;
-  using V = typename Ops<Pr>::V;
-  constexpr int NT = kDir3Cols / 16, LDC = kDir3Cols + 1;
+  using V = typename Grp<Pr>::V;
+  constexpr int NT = kDir3Cols / 16;
   if (ep.flag && *ep.flag) return;
   extern __shared__ char smem_raw[];
   Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int mtiles = (n3 + 15) / 16;
+  const int ldt = lds_ld<Tmid>(mtiles);
   const int c0 = blockIdx.x * kDir3Cols;
   acc_t acc[kMaxTilesPerWave][NT];
   // step 1: A = Wf (rows k3, contracted j3), B = X (contracted j3, columns c)
-  auto loadA1 = [&](int j3, int mt) -> V {
-    return j3 < npad3 ? (V)Wf[(long long)(mt * 16 + col) * npad3 + j3] : V(0);
-  };
-  auto loadB1 = [&](int j3, int t) -> V {
+  auto loadA1 = [&](int j3, int mt, V (&v)[4]) { ld4(Wf + (long long)(mt * 16 + col) * npad3 + j3, v); };
+  auto loadB1 = [&](int j3, int t, V (&v)[4]) {
     const int c = c0 + t * 16 + col;
-    return (c < C && j3 < n3) ? (V)X[(long long)j3 * C + c] : V(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (c < C && j3 + j < n3) ? (V)X[(long long)(j3 + j) * C + c] : V(0);
   };
   // scaling by the eigenvalue sums between the two contractions
   auto mid = [&](int k3, int t, double v) -> double {
     const int c = c0 + t * 16 + col;
     return (k3 < n3 && c < C) ? v / (ep.lamK[k3] + ep.lam2[c / ep.n1] + ep.lam1[c % ep.n1]) : 0.0;
   };
-  auto loadA2 = [&](int k3, int mt) -> V {
-    return k3 < npad3 ? (V)Wb[(long long)(mt * 16 + col) * npad3 + k3] : V(0);
-  };
-  two_step<Pr, NT>(acc, n3, n3, mtiles, wave, grp, col, sT, LDC, loadA1, loadB1, mid, loadA2);
+  auto loadA2 = [&](int k3, int mt, V (&v)[4]) { ld4(Wb + (long long)(mt * 16 + col) * npad3 + k3, v); };
+  two_step<Pr, NT>(acc, n3, n3, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
     const int mt = wave + 4 * m;
@@ -549,8 +627,8 @@ igafd_status apply_fused(igafd_ctx* c, const Tw* const* Wf, const Tw* const* Wb,
   e_lam.lam1 = d[0].lam;
   e_lam.lam2 = d[1].lam;
   const dim3 gs((unsigned)((n1 + kSliceCols - 1) / kSliceCols), (unsigned)n3);
-  const size_t lds_s = sizeof(T) * ((n2 + 15) / 16 * 16) * (kSliceCols + 1);
-  const size_t lds_3 = sizeof(T) * ((n3 + 15) / 16 * 16) * (kDir3Cols + 1);
+  const size_t lds_s = sizeof(T) * (size_t)kSliceCols * lds_ld<T>((n2 + 15) / 16);
+  const size_t lds_3 = sizeof(T) * (size_t)kDir3Cols * lds_ld<T>((n3 + 15) / 16);
   const int C = n1 * n2;
   hipLaunchKernelGGL((k_slice<Pr, double, T, Tw, T>), gs, dim3(kBlock), lds_s, st, r, b0, Wf[0], Wf[1], n1, n2,
                      d[0].npad, d[1].npad, e_in);
