@@ -78,15 +78,24 @@ def kernel_report(api, torch, ctx, reps=50, precisions=("fp64", "fp32", "bf16"))
     by = spmv_bytes(ctx)
     gbs = by / (t_spmv * 1e-3) / 1e9
     fl = fd_flops(ctx)
-    log(f"spmv {t_spmv * 1e3:.1f} us = {gbs:.0f} GB/s; FD " +
+    name, tag = spmv_kernel_name(api, ctx)
+    log(f"spmv [{name}] {t_spmv * 1e3:.1f} us = {gbs:.0f} GB/s; FD " +
         " ".join(f"{pr} {t * 1e3:.1f} us" for pr, t in t_fd.items()))
-    return {"t_spmv": t_spmv, "t_fd": t_fd, "bytes": by, "gbs": gbs, "fd_flops": fl}
+    return {"t_spmv": t_spmv, "t_fd": t_fd, "bytes": by, "gbs": gbs, "fd_flops": fl, "kernel": name,
+            "kernel_tag": tag}
 
 
-def profiled_traffic(workload_tag):
-    """HBM/fabric bytes per A-product launch from the committed counter
-    summaries (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy),
-    used only while the A-product source is the one that was measured."""
+def spmv_kernel_name(api, ctx):
+    s = api.igafd_get_shape(ctx)
+    if s["tile_b2"] > 0:
+        return f"k_spmv_tile<p={ctx.p}> ({s['tile_b2']}x{s['tile_b3']} lines) + k_spmv_combine", "tile"
+    return f"k_spmv<R={s['spmv_rows']}>", "row"
+
+
+def profiled_traffic(kernel_tag, workload_tag):
+    """HBM/fabric bytes per A product from the committed counter summaries
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy), used only
+    while the A-product source is the one that was measured."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1602_01636_amd", "csrc", "spmv.hip")
@@ -97,16 +106,16 @@ def profiled_traffic(workload_tag):
             key, _, val = line.strip().partition(": ")
             if key.startswith("traffic_"):
                 fields[key] = val.strip()
-        if (fields.get("traffic_kernel") == "k_spmv" and fields.get("traffic_workload") == workload_tag
+        if (fields.get("traffic_kernel") == kernel_tag and fields.get("traffic_workload") == workload_tag
                 and fields.get("traffic_source_sha256_16") == sha):
             return int(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
 
 
 def roofline(kr, workload_tag=None):
-    traffic, source = profiled_traffic(workload_tag) if workload_tag else (None, None)
+    traffic, source = profiled_traffic(kr["kernel_tag"], workload_tag) if workload_tag else (None, None)
     out = {"bound": "hbm", "achieved": kr["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": kr["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_spmv (A x)",
+           "frac": kr["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": kr["kernel"],
            "algorithmic_bytes": kr["bytes"]}
     if traffic:
         out["traffic_source"] = source

@@ -164,6 +164,14 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
  * buffer, so call it at setup time, not inside a timed or captured region. */
 igafd_status igafd_autotune(igafd_ctx* ctx, int fd_tiles, int spmv_rows);
 
+/* Kernel shape in use (host outputs, any may be NULL): tile_b2, tile_b3 = the
+ * lines per tile of the 3D tiled A product (0 when the row-parallel kernel
+ * with spmv_rows rows per thread is used); fd_fused = 1 when the 3D FD apply
+ * runs as three fused passes, fd_tiles = row tiles per wave of the generic
+ * mode products otherwise. */
+igafd_status igafd_get_shape(const igafd_ctx* ctx, int* spmv_rows, int* tile_b2, int* tile_b3, int* fd_fused,
+                             int* fd_tiles);
+
 /* Diagonals of A and P (N doubles each, device; either may be NULL). */
 igafd_status igafd_diagonals(igafd_ctx* ctx, double* diagA_dev, double* diagP_dev);
 

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "igafd_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(igafd_solve_opts),
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
     "igafd_scaling_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
     "igafd_set_scaling_diag_ratio": (C.c_int, [C.c_void_p]),
     "igafd_mlp_num_params": (C.c_int, []),
@@ -160,13 +161,14 @@ def coefficient_params(coef: dict):
 class Context:
     """Owner of an igafd_ctx handle; `handle` is passed to the igafd_* calls."""
 
-    def __init__(self, handle, n, N, nnz, band_bytes, dim):
+    def __init__(self, handle, n, N, nnz, band_bytes, dim, degree=None):
         self.handle = handle
         self.n = n
         self.N = N
         self.nnz = nnz
         self.band_bytes = band_bytes
         self.dim = dim
+        self.p = degree
 
     @property
     def shape(self):
@@ -215,7 +217,7 @@ def igafd_setup(problem: dict, stream=None) -> Context:
     h = C.c_void_p()
     _check(lib().igafd_setup(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
     n, N, nnz, bb = igafd_sizes(h)
-    return Context(h, n, N, nnz, bb, d)
+    return Context(h, n, N, nnz, bb, d, pr.degree)
 
 
 def _h(ctx):
@@ -305,6 +307,13 @@ def igafd_solve_batched(ctxs, bs, us, rtol=1e-8, maxit=2000, precision="fp64", f
 def igafd_autotune(ctx: Context, fd_tiles=0, spmv_rows=0):
     """Kernel shape of one problem (0, 0: time the candidates and keep the fastest)."""
     _check(lib().igafd_autotune(_h(ctx), int(fd_tiles), int(spmv_rows)))
+
+
+def igafd_get_shape(ctx: Context) -> dict:
+    """Kernel shape in use: {"spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles"}."""
+    v = [C.c_int() for _ in range(5)]
+    _check(lib().igafd_get_shape(_h(ctx), *[C.byref(x) for x in v]))
+    return dict(zip(("spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles"), [x.value for x in v]))
 
 
 def igafd_get_eigen(ctx: Context, direction: int):

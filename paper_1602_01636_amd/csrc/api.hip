@@ -57,15 +57,19 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ b, c
 
 // One block: sum partial[0..count) (and partial[count..2 count) when two
 // sums are pending) in a fixed order, then the scalar step of CG.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int count, int two, int which,
-                                                   SolverState* __restrict__ s, double* __restrict__ hist) {
+constexpr int kReduceBlock = 1024;  // one wide block: a few independent loads per thread
+
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restrict__ partial, int count, int two,
+                                                         int which, SolverState* __restrict__ s,
+                                                         double* __restrict__ hist) {
   if (which != RED_BB_RR && which != RED_RHO0 && which != RED_TRUE && s->flag != FLAG_RUNNING) return;
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < count; k += kBlock) {
+#pragma unroll 4
+  for (int k = threadIdx.x; k < count; k += kReduceBlock) {
     a += partial[k];
     if (two) b += partial[count + k];
   }
-  block_sum2(a, b);
+  block_sum2<kReduceBlock>(a, b);
   if (threadIdx.x != 0) return;
   switch (which) {
     case RED_BB_RR:  // a = (b,b), b = (r,r)
@@ -344,7 +348,8 @@ igafd_status reduce(igafd_ctx* c, int count, int two, int which, double* hist) {
     set_error("internal: reduction count larger than the partial-sum buffer");
     return IGAFD_ERR_ARG;
   }
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, c->stream, c->partial, count, two, which, c->state, hist);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceBlock), 0, c->stream, c->partial, count, two, which, c->state,
+                     hist);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
@@ -994,6 +999,20 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
     return IGAFD_ERR_ARG;
   }
   return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
+}
+
+igafd_status igafd_get_shape(const igafd_ctx* c, int* spmv_rows, int* tile_b2, int* tile_b3, int* fd_fused,
+                             int* fd_tiles) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (spmv_rows) *spmv_rows = c->spmv_rows;
+  if (tile_b2) *tile_b2 = c->tile_b2;
+  if (tile_b3) *tile_b3 = c->tile_b3;
+  if (fd_fused) *fd_fused = (c->fd_fused && fd_fused_ok(c)) ? 1 : 0;
+  if (fd_tiles) *fd_tiles = c->fd_tiles;
+  return IGAFD_OK;
 }
 
 igafd_status igafd_autotune(igafd_ctx* c, int fd_tiles, int spmv_rows) {

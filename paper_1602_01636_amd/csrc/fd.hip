@@ -337,7 +337,7 @@ __host__ __device__ inline int lds_ld(int mtiles) {
 // the block holds its rows contiguously, so step 2 reads 16-byte vectors),
 // rescaled on the way by `mid`.  Operand loads are double buffered: while the
 // MFMAs of one stage run, the loads of the next are in flight.
-template <class Pr, int NT, typename Tmid, typename A1, typename B1, typename Mid, typename A2>
+template <class Pr, int NT, bool SYNC_MID, typename Tmid, typename A1, typename B1, typename Mid, typename A2>
 __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], int K1, int K2, int mtiles, int wave,
                                 int grp, int col, Tmid* sT, int ldt, A1 loadA1, B1 loadB1, Mid mid, A2 loadA2) {
   using acc_t = typename Pr::acc;
@@ -431,7 +431,9 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
     if (k0 + 2 * STEP < K1) load1(k0 + 2 * STEP, av[0], bv[0]);
     if (k0 + STEP < K1) compute(k0 + STEP, K1, av[1], bv[1]);
   }
-  // intermediate tile to LDS, transposed (rows past the problem hold zeros)
+  // intermediate tile to LDS, transposed (rows past the problem hold zeros);
+  // SYNC_MID: step 1 read its B operand from the same LDS area
+  if (SYNC_MID) __syncthreads();
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
     const int mt = wave + 4 * m;
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tou
   auto mid = [&](int, int, double v) { return v; };
   // step 2: A = V2 (rows i2, contracted j2), B = the LDS tile
   auto loadA2 = [&](int j2, int mt, V (&v)[4]) { ld4(V2 + (long long)(mt * 16 + col) * npad2 + j2, v); };
-  two_step<Pr, NT>(acc, n1, n2, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
+  two_step<Pr, NT, false>(acc, n1, n2, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
   double dot = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
@@ -560,20 +562,48 @@ __global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmi
   const int ldt = lds_ld<Tmid>(mtiles);
   const int c0 = blockIdx.x * kDir3Cols;
   acc_t acc[kMaxTilesPerWave][NT];
+  // the block's 32 input columns, staged transposed in LDS (column c holds its
+  // n3 values contiguously, zeros up to the padded height) with 16-byte
+  // loads along the rows; the step-1 B operand is read from there
+  {
+    constexpr int VEC = 16 / (int)sizeof(Tmid), PER_ROW = kDir3Cols / VEC;
+    const int rows = mtiles * 16;
+    for (int idx = threadIdx.x; idx < rows * PER_ROW; idx += kBlock) {
+      const int j3 = idx / PER_ROW, cq = (idx - j3 * PER_ROW) * VEC;
+      const int c = c0 + cq;
+      Tmid v[VEC];
+      if (j3 < n3 && c + VEC <= C) {
+        const Tmid* src = X + (long long)j3 * C + c;
+        if constexpr (VEC == 2) {
+          const d2u_t u = *reinterpret_cast<const d2u_t*>(src);
+          v[0] = u.x;
+          v[1] = u.y;
+        } else {
+          const f4u_t u = *reinterpret_cast<const f4u_t*>(src);
+          v[0] = u.x;
+          v[1] = u.y;
+          v[2] = u.z;
+          v[3] = u.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) v[j] = (j3 < n3 && c + j < C) ? X[(long long)j3 * C + c + j] : Tmid(0);
+      }
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) sT[(cq + j) * ldt + j3] = v[j];
+    }
+    __syncthreads();
+  }
   // step 1: A = Wf (rows k3, contracted j3), B = X (contracted j3, columns c)
   auto loadA1 = [&](int j3, int mt, V (&v)[4]) { ld4(Wf + (long long)(mt * 16 + col) * npad3 + j3, v); };
-  auto loadB1 = [&](int j3, int t, V (&v)[4]) {
-    const int c = c0 + t * 16 + col;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = (c < C && j3 + j < n3) ? (V)X[(long long)(j3 + j) * C + c] : V(0);
-  };
+  auto loadB1 = [&](int j3, int t, V (&v)[4]) { ld4(sT + (t * 16 + col) * ldt + j3, v); };
   // scaling by the eigenvalue sums between the two contractions
   auto mid = [&](int k3, int t, double v) -> double {
     const int c = c0 + t * 16 + col;
     return (k3 < n3 && c < C) ? v / (ep.lamK[k3] + ep.lam2[c / ep.n1] + ep.lam1[c % ep.n1]) : 0.0;
   };
   auto loadA2 = [&](int k3, int mt, V (&v)[4]) { ld4(Wb + (long long)(mt * 16 + col) * npad3 + k3, v); };
-  two_step<Pr, NT>(acc, n3, n3, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
+  two_step<Pr, NT, true>(acc, n3, n3, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
     const int mt = wave + 4 * m;
@@ -716,6 +746,8 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
 }
 
 }  // namespace
+
+bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c); }
 
 int fd_dot_blocks(const igafd_ctx* c) { return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c); }
 

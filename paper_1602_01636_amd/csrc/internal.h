@@ -137,4 +137,5 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
 int fd_dot_blocks(const igafd_ctx* c);
 int fd_dot_blocks_max(const igafd_ctx* c);
 int fd_npad(int n);
+bool fd_fused_ok(const igafd_ctx* c);
 }  // namespace igafd

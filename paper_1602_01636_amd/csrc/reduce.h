@@ -25,9 +25,11 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
-// Two simultaneous sums (e.g. (r,z) and (r,z_old)).
+// Two simultaneous sums (e.g. (r,z) and (r,z_old)) over a block of NT
+// threads; the results are valid in thread 0.
+template <int NT = kBlock>
 __device__ inline void block_sum2(double& a, double& b) {
-  __shared__ double part[2][kBlock / 64];
+  __shared__ double part[2][NT / 64];
   a = wave_sum(a);
   b = wave_sum(b);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -39,7 +41,7 @@ __device__ inline void block_sum2(double& a, double& b) {
   __syncthreads();
   if (threadIdx.x == 0) {
     a = b = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       a += part[0][w];
       b += part[1][w];
     }
