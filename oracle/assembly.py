@@ -202,3 +202,17 @@ def quadrature_points(problem):
         xs.append(xi.reshape(-1, mesh.d))
         ws.append(w.reshape(-1))
     return np.concatenate(xs), np.concatenate(ws)
+
+
+def q_spectral_bounds(problem):
+    """Sec. 3 Prop. 1: (qmin, qmax) = the smallest and largest eigenvalue of
+    Q = |det J| J^-1 (kappa I) J^-T over the Gauss points of the mesh.  With A
+    and P assembled by the same rule, every eigenvalue of P^-1 A lies in
+    [qmin, qmax]."""
+    xi, _ = quadrature_points(problem)
+    lo, hi = np.inf, -np.inf
+    for k in range(0, len(xi), 1 << 18):
+        Q, _, _ = geometry.q_matrix(problem, xi[k:k + (1 << 18)])
+        ev = np.linalg.eigvalsh(Q)
+        lo, hi = min(lo, ev[:, 0].min()), max(hi, ev[:, -1].max())
+    return float(lo), float(hi)

@@ -179,3 +179,34 @@ def test_scaling_targets_identity_zero_and_exact_ratio_helps():
     _, i0 = pcg.solve(prob, A, F, b)
     _, i1 = pcg.solve(prob, A, F, b, scaling=S)
     assert i1["iters"] <= i0["iters"]
+
+
+def test_q_spectral_bounds_ring_closed_form():
+    # thick ring: Q = diag(w, 1/w, w), w = pi (1 + xi1) / 2, so the extremes
+    # over the Gauss points follow from the direction-1 Gauss abscissae alone
+    E, p = 5, 2
+    prob = synth.uniform_problem(3, [E, 3, 4], p, geometry={"kind": "ring"})
+    g, _ = np.polynomial.legendre.leggauss(p + 1)
+    xi1 = ((np.arange(E)[:, None] + 0.5 * (g[None, :] + 1.0)) / E).ravel()
+    w = np.pi * (1.0 + xi1) / 2.0
+    lo, hi = assembly.q_spectral_bounds(prob)
+    assert abs(lo - np.minimum(w, 1 / w).min()) < 1e-13
+    assert abs(hi - np.maximum(w, 1 / w).max()) < 1e-13
+    # identity map, kappa = 1: Q = I
+    lo, hi = assembly.q_spectral_bounds(synth.uniform_problem(3, 3, 2))
+    assert abs(lo - 1) < 1e-14 and abs(hi - 1) < 1e-14
+
+
+def test_q_spectral_bounds_contain_generalised_eigenvalues():
+    # Prop. 1 for the discrete matrices: the eigenvalues of the pencil (A, P)
+    # lie in [qmin, qmax] (warped map with a coefficient, so Q is full)
+    import scipy.linalg
+    prob = synth.uniform_problem(3, [3, 4, 3], 2, geometry=synth.warped_geometry(9),
+                                 coefficient=synth.sincos_coefficient(0.4, 1, 2, 0.2, 0.7))
+    A = assembly.assemble_matrix(prob).toarray()
+    P = fd.kron_P(fd.setup(prob))
+    ev = scipy.linalg.eigh(A, P, eigvals_only=True)
+    lo, hi = assembly.q_spectral_bounds(prob)
+    assert lo > 0 and ev.min() >= lo * (1 - 1e-12) and ev.max() <= hi * (1 + 1e-12)
+    # and the bound is not loose by orders of magnitude
+    assert ev.max() / ev.min() > 0.2 * hi / lo
