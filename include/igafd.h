@@ -175,6 +175,15 @@ igafd_status igafd_get_shape(const igafd_ctx* ctx, int* spmv_rows, int* tile_b2,
 /* Diagonals of A and P (N doubles each, device; either may be NULL). */
 igafd_status igafd_diagonals(igafd_ctx* ctx, double* diagA_dev, double* diagP_dev);
 
+/* A-priori bounds of the preconditioned spectrum (Sec. 3, Prop. 1): every
+ * eigenvalue of P^-1 A lies in [qmin, qmax], the smallest and largest
+ * eigenvalue of Q = kappa |det J| J^-1 J^-T over the Gauss points of the
+ * mesh (A and P are assembled with the same rule, so the bound holds for the
+ * discrete matrices); qmax / qmin bounds the condition number that drives
+ * the CG iteration count.  qmin, qmax: host outputs.  Synchronises the
+ * context's stream. */
+igafd_status igafd_spectral_bounds(igafd_ctx* ctx, double* qmin, double* qmax);
+
 /* Host copy of U_d (n_d x n_d row-major, U[i][k] = component i of eigenvector k,
  * U^T M U = I) and of the eigenvalues D_d for direction dir (0-based). */
 igafd_status igafd_get_eigen(const igafd_ctx* ctx, int dir, double* U_host, double* lam_host);

@@ -74,6 +74,7 @@ _SIGNATURES = {
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
+    "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "igafd_scaling_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
     "igafd_set_scaling_diag_ratio": (C.c_int, [C.c_void_p]),
     "igafd_mlp_num_params": (C.c_int, []),
@@ -307,6 +308,13 @@ def igafd_solve_batched(ctxs, bs, us, rtol=1e-8, maxit=2000, precision="fp64", f
 def igafd_autotune(ctx: Context, fd_tiles=0, spmv_rows=0):
     """Kernel shape of one problem (0, 0: time the candidates and keep the fastest)."""
     _check(lib().igafd_autotune(_h(ctx), int(fd_tiles), int(spmv_rows)))
+
+
+def igafd_spectral_bounds(ctx: Context):
+    """(qmin, qmax): every eigenvalue of P^-1 A lies in [qmin, qmax] (Prop. 1)."""
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib().igafd_spectral_bounds(_h(ctx), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
 
 
 def igafd_get_shape(ctx: Context) -> dict:

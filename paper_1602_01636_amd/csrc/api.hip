@@ -1001,6 +1001,14 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
   return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
 }
 
+igafd_status igafd_spectral_bounds(igafd_ctx* c, double* qmin, double* qmax) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  return spectral_bounds(c, qmin, qmax);
+}
+
 igafd_status igafd_get_shape(const igafd_ctx* c, int* spmv_rows, int* tile_b2, int* tile_b3, int* fd_fused,
                              int* fd_tiles) {
   if (!c) {

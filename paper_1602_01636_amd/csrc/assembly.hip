@@ -373,6 +373,110 @@ __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, doubl
   }
 }
 
+// Extreme eigenvalues of a symmetric positive definite 2x2 / 3x3 matrix.
+// 2x2: closed form, the small one as det / large (no cancellation).  3x3:
+// cyclic Jacobi rotations (each zeroes one off-diagonal pair; the diagonal
+// converges quadratically to the eigenvalues, accurate to roundoff also for
+// repeated eigenvalues, where closed forms of the cubic lose half the digits).
+__device__ inline void sym_extremes(int d, const double Q[3][3], double& lo, double& hi) {
+  if (d == 2) {
+    const double m = 0.5 * (Q[0][0] + Q[1][1]), h = 0.5 * (Q[0][0] - Q[1][1]);
+    hi = m + sqrt(h * h + Q[0][1] * Q[0][1]);
+    lo = (Q[0][0] * Q[1][1] - Q[0][1] * Q[0][1]) / hi;
+    return;
+  }
+  double a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) a[i][j] = Q[i][j];
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off <= 1e-36 * dia) break;
+    for (int k = 0; k < 3; ++k) {
+      const int p = k == 2 ? 1 : 0, q = k == 0 ? 1 : 2;
+      const double apq = a[p][q];
+      if (fabs(apq) <= 1e-300) continue;
+      // rotation angle with tan(2 phi) = 2 a_pq / (a_qq - a_pp); t = tan(phi), the smaller root
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      a[p][p] -= t * apq;
+      a[q][q] += t * apq;
+      a[p][q] = a[q][p] = 0.0;
+      const int r = 3 - p - q;
+      const double arp = a[r][p], arq = a[r][q];
+      a[r][p] = a[p][r] = c * arp - s * arq;
+      a[r][q] = a[q][r] = s * arp + c * arq;
+    }
+  }
+  lo = fmin(a[0][0], fmin(a[1][1], a[2][2]));
+  hi = fmax(a[0][0], fmax(a[1][1], a[2][2]));
+}
+
+// min / max over the Gauss points of the extreme eigenvalues of
+// Q = kappa |det J| J^-1 J^-T (Sec. 2.1 eq. Q).  Grid-stride over all points
+// (nq[l] = points along direction l, flat index i1 + nq0 (i2 + nq1 i3));
+// one (min, max) pair per block in part[blockIdx.x], part[gridDim.x + blockIdx.x].
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_qbounds(const double* __restrict__ qx0, const double* __restrict__ qx1,
+                                                    const double* __restrict__ qx2, GeomDesc g, int nq0, int nq1,
+                                                    int nq2, double* __restrict__ part) {
+  double lo = INFINITY, hi = -INFINITY;
+  const long long total = (long long)nq0 * nq1 * nq2;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long long)gridDim.x * kBlock) {
+    const int i1 = (int)(i % nq0);
+    const long long rest = i / nq0;
+    const int i2 = (int)(rest % nq1), i3 = (int)(rest / nq1);
+    const double xi[3] = {qx0[i1], qx1[i2], D == 3 ? qx2[i3] : 0.0};
+    double x[3], J[3][3], A[3][3] = {};
+    map_eval<D>(g, xi, x, J);
+    const double det = fabs(adjugate<D>(J, A));
+    const double k = kappa_eval(g, x) / det;
+    double Q[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double s = 0.0;
+        for (int l = 0; l < D; ++l) s += A[a][l] * A[b][l];
+        Q[a][b] = k * s;
+      }
+    double l0, l1;
+    sym_extremes(D, Q, l0, l1);
+    lo = fmin(lo, l0);
+    hi = fmax(hi, l1);
+  }
+  // min / max are exact: any reduction order gives the same result
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_down(lo, off, 64));
+    hi = fmax(hi, __shfl_down(hi, off, 64));
+  }
+  __shared__ double slo[kBlock / 64], shi[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    slo[wid] = lo;
+    shi[wid] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      lo = fmin(lo, slo[w]);
+      hi = fmax(hi, shi[w]);
+    }
+    part[blockIdx.x] = lo;
+    part[gridDim.x + blockIdx.x] = hi;
+  }
+}
+
+__global__ void k_minmax(const double* __restrict__ part, int count, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int k = 0; k < count; ++k) {
+    lo = fmin(lo, part[k]);
+    hi = fmax(hi, part[count + k]);
+  }
+  out[0] = lo;
+  out[1] = hi;
+}
+
 // feat[i] = (acc[i][0..6] / acc[i][7], p) in FP32
 __global__ void k_features_finish(const double* __restrict__ acc, float* __restrict__ feat, long long N, int p) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -541,6 +645,33 @@ igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b) {
   }
   IGAFD_HIP_CHECK(hipMemsetAsync(b, 0, sizeof(double) * c->N, c->stream));
   return dispatch<LoadOp>(c->dim, c->p, c, rhs_kind, b);
+}
+
+igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax) {
+  const int nq0 = c->dir[0].nel * c->dir[0].q, nq1 = c->dir[1].nel * c->dir[1].q;
+  const int nq2 = c->dim == 3 ? c->dir[2].nel * c->dir[2].q : 1;
+  // partial buffer: 2 * npartial doubles = blocks (min, max) pairs + the result
+  const int blocks = c->npartial - 1 < 1024 ? c->npartial - 1 : 1024;
+  double* out = c->partial + 2 * blocks;
+  if (blocks < 1 || 2 * blocks + 2 > 2 * c->npartial) {
+    set_error("internal: partial-sum buffer too small for the spectral bounds");
+    return IGAFD_ERR_ARG;
+  }
+  if (c->dim == 3)
+    hipLaunchKernelGGL(k_qbounds<3>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
+                       c->ddir[2].qx, c->geom, nq0, nq1, nq2, c->partial);
+  else
+    hipLaunchKernelGGL(k_qbounds<2>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
+                       c->ddir[1].qx, c->geom, nq0, nq1, 1, c->partial);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(64), 0, c->stream, c->partial, blocks, out);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  double h[2];
+  IGAFD_HIP_CHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  if (qmin) *qmin = h[0];
+  if (qmax) *qmax = h[1];
+  return IGAFD_OK;
 }
 
 igafd_status diagonals(igafd_ctx* c, double* dA, double* dP) {

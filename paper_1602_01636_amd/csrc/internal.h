@@ -125,6 +125,7 @@ igafd_status diagonals(igafd_ctx* c, double* dA, double* dP);
 igafd_status features(igafd_ctx* c, float* feat);
 igafd_status scaling_targets(igafd_ctx* c, float* t);
 igafd_status diag_ratio_scaling(igafd_ctx* c, double* S);
+igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax);
 // spmv.hip
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);

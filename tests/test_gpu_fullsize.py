@@ -8,6 +8,7 @@ what it can compute one by one or whole:
   touch those rows): 1e-12 relative to sum_j |a_ij x_j| per row;
 * the whole FD apply P^-1 r (the oracle's mode products are cheap): FP64
   1e-11, FP32 1e-4, BF16 5e-2 relative (as in the small-size tests);
+* the Prop. 1 spectral bounds against their closed form on the ring;
 * the solve: the library's FP64 true residual <= 1e-8, and on the sampled
   rows the oracle's own residual b_i - (A u)_i of the library's u is within
   1e-8 ||b|| plus the row-assembly rounding.
@@ -84,6 +85,11 @@ def check_fd(api, ctx, F, prec, tol, seed):
 def test_thick_ring_128_p3(api):
     prob = synth.thick_ring(E=128, p=3)
     with api.igafd_setup(prob) as ctx:
+        # Prop. 1 bounds against their closed form on the ring (Q = diag(w, 1/w, w))
+        g, _ = np.polynomial.legendre.leggauss(4)
+        w = np.pi * (1.0 + ((np.arange(128)[:, None] + 0.5 * (g[None, :] + 1.0)) / 128).ravel()) / 2.0
+        lo, hi = api.igafd_spectral_bounds(ctx)
+        assert abs(lo - np.minimum(w, 1 / w).min()) < 1e-13 and abs(hi - np.maximum(w, 1 / w).max()) < 1e-13
         rows = sample_rows(ctx.n, 40, 1)
         A_r, b, bg = check_rows(api, ctx, prob, rows, 2)
         F = fd.setup(prob)

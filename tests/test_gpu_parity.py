@@ -89,6 +89,16 @@ def test_apply_A_kernel_shapes(api, name, tile, rng, monkeypatch):
 
 
 @pytest.mark.parametrize("name,prob", PROBLEMS, ids=IDS)
+def test_spectral_bounds_match_oracle(api, name, prob):
+    # Prop. 1 bounds: extreme eigenvalues of Q over all Gauss points (closed
+    # form on the device, eigvalsh in the oracle)
+    lo, hi = assembly.q_spectral_bounds(prob)
+    with api.igafd_setup(prob) as ctx:
+        glo, ghi = api.igafd_spectral_bounds(ctx)
+    assert abs(glo - lo) <= 1e-12 * abs(lo) and abs(ghi - hi) <= 1e-12 * abs(hi)
+
+
+@pytest.mark.parametrize("name,prob", PROBLEMS, ids=IDS)
 def test_load_vector_matches_oracle(api, name, prob):
     with api.igafd_setup(prob) as ctx:
         for rhs in (synth.RHS_SINPROD, synth.RHS_PAPER_POLY, synth.RHS_BUBBLE):
