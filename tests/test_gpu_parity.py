@@ -121,6 +121,40 @@ def test_precond_matches_oracle(api, name, prob, rng):
             assert err < tol, (prec, err)
 
 
+def test_precond_ragged_row_tiles(api, rng, monkeypatch):
+    # n2 = 65, n3 = 66: the last MFMA row tile of those directions holds one or
+    # two rows; applies against the oracle (also scaled) and the solve against
+    # the six separate mode products
+    prob = synth.uniform_problem(3, [10, 64, 65], 3, geometry=synth.warped_geometry(6),
+                                 coefficient=synth.sincos_coefficient(0.3, 1, 1, 0.2, 0.4))
+    F = fd.setup(prob)
+    with api.igafd_setup(prob) as ctx:
+        assert tuple(ctx.n[:3]) == (11, 65, 66) and api.igafd_get_shape(ctx)["fd_fused"] == 1
+        r = rng.standard_normal(ctx.N)
+        ref = fd.fd_apply(F, r)
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2)):
+            s = to_dev(np.zeros(ctx.N))
+            api.igafd_apply_precond(ctx, prec, to_dev(r), s)
+            assert rel(to_host(s), ref) < tol, prec
+        S = np.exp(0.1 * rng.standard_normal(ctx.N))
+        api.igafd_set_scaling(ctx, to_dev(S))
+        s = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_precond(ctx, "fp64", to_dev(r), s)
+        assert rel(to_host(s), S * fd.fd_apply(F, S * r)) < 1e-11
+        api.igafd_set_scaling(ctx, None)
+        b = to_dev(np.zeros(ctx.N))
+        api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
+        u = to_dev(np.zeros(ctx.N))
+        info = api.igafd_solve(ctx, b, u)
+    # the same solve with the six separate mode products
+    monkeypatch.setenv("IGAFD_FD_FUSED", "0")
+    with api.igafd_setup(prob) as ctx6:
+        assert api.igafd_get_shape(ctx6)["fd_fused"] == 0
+        u6 = to_dev(np.zeros(ctx6.N))
+        info6 = api.igafd_solve(ctx6, b, u6)
+    assert info["iters"] == info6["iters"] and rel(to_host(u), to_host(u6)) < 1e-10
+
+
 @pytest.mark.parametrize("name,prob", PROBLEMS, ids=IDS)
 def test_solve_matches_oracle(api, name, prob):
     A, F = oracle_of(name, prob)
