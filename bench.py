@@ -241,6 +241,7 @@ def run_ring(args, api, torch, synth):
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(iters, n, p, ctx.nnz)
         log(f"cpu baseline {cpu['value']:.2f} s ({cpu['sample']})")
+    qlo, qhi = api.igafd_spectral_bounds(ctx)
     workload = {"workload": f"thick quarter ring, p={p}, {E}^3 elements, n={n}/dir, N={N} dofs, "
                             f"f=3pi^2 prod sin(pi x_i), FP64 FD-preconditioned CG, rtol 1e-8",
                 "elements": E, "degree": p, "N": N, "nnz": ctx.nnz}
@@ -249,6 +250,7 @@ def run_ring(args, api, torch, synth):
         "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
         "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
         "variants": variants, "setup_s": t_setup, "wall_s_timed": wall,
+        "spectral_bounds": [qlo, qhi], "kappa_bound": qhi / qlo,
         "roofline": roofline(kr, f"thick_ring E={E} p={p}"), "fd_roofline": fd_roofline(kr),
         "cpu_baseline": cpu})
     ctx.close()
@@ -365,6 +367,8 @@ def run_learned(args, api, torch, synth):
     ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, use_scaling=True)
     res["exact_ratio"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"]}
     log(f"plain {res['plain']['iters']} learned {res['learned']['iters']} exact {res['exact_ratio']['iters']}")
+    qlo, qhi = api.igafd_spectral_bounds(ctx)
+    res["plain"]["kappa_bound"] = qhi / qlo
     kr = kernel_report(api, torch, ctx, precisions=("fp64",))
     ms_per_step = 1e3 * sum(times) / len(times)
     workload = {"workload": f"warped unit cube (seed 10000), kappa=1+0.5 sin(2pi x)cos(2pi y), p={p}, {E}^3 elements, "
