@@ -23,6 +23,9 @@ Modules
                 apply of P^-1 (Sec. 4.1 Alg. 1, Sec. 5.1 Alg. 3), the
                 explicit Kronecker form of P (Sec. 3 eq. prec)
     pcg         preconditioned CG, flexible CG, scaled preconditioner
+    multipatch  L-shaped three-patch domain with C^0 interfaces and the
+                overlapping additive Schwarz preconditioners P_EAS, P_IAS
+                (Sec. 6 eq. Peas, eq. Pias)
     mlp         FP64 reference of the learned diagonal scaling network
 
 Parity status: every function has a pin in tests/test_oracle_*.py except
