@@ -194,6 +194,41 @@ igafd_status igafd_get_eigen(const igafd_ctx* ctx, int dir, double* U_host, doub
 igafd_status igafd_univariate(int degree, int nknots, const double* knots, int quad,
                               double* M, double* K, double* U, double* lam, int* n_out);
 
+/* ---------------- multi-patch: L-shaped domain, additive Schwarz ----------------
+ * Sec. 6 (eq. Pias) and the multi-patch experiment of Sec. 7: the L-shaped
+ * domain [0,1]^2 without (1/2,1] x (1/2,1], made of three square patches
+ * (the corner patch [0,1/2]^2, the patch above it and the patch to its
+ * right) with C^0 continuity across the two interfaces and the Dirichlet
+ * Poisson problem (K = I) on it.  The overlapping subdomains are the two
+ * pairs of patches sharing an interface (Theta_1 = corner + upper patch,
+ * Theta_2 = corner + right patch); the preconditioner is
+ *     P_IAS^-1 = sum_i R_i^T P_i^-1 R_i,
+ * P_i the Kronecker-sum preconditioner of Theta_i in its own parameter domain
+ * (one patch along one direction, two joined by a p-fold knot along the
+ * other), applied by fast diagonalisation.
+ *
+ * Layout: vectors of an L-shaped context live on the bounding square's grid,
+ * n x n with n = 2h + 1 (h = interior functions per patch and direction,
+ * direction 1 fastest); the entries with i1 >= h and i2 >= h are not unknowns
+ * of the problem.  Every entry point of such a context writes zeros there
+ * and ignores what its inputs hold there.  igafd_apply_A, igafd_apply_precond
+ * (P_IAS^-1, any precision), igafd_load_vector (f evaluated at x = xi),
+ * igafd_solve and igafd_autotune work as for one patch; the scaled
+ * preconditioner, the diagonals, the learned-scaling calls, the spectral
+ * bounds and igafd_solve_batched return IGAFD_ERR_ARG.
+ */
+
+/* Setup of the L-shaped problem: every patch carries, in both directions, the
+ * open knot vector `knots` on [0,1] (host, nknots values, copied), so the
+ * patch meshes are conforming.  Assembles A on the device and factors the two
+ * subdomains' univariate matrices.  `stream` as in igafd_setup. */
+igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, void* stream, igafd_ctx** out);
+
+/* *hole = h, the first index (in both directions) of the grid entries that are
+ * not unknowns, or -1 for a single-patch context; *ndofs = number of unknowns
+ * (N - (n - h)^2, or N).  Either output may be NULL. */
+igafd_status igafd_lshape_corner(const igafd_ctx* ctx, int* hole, long long* ndofs);
+
 /* ---------------- learned diagonal scaling (S P^-1 S) ----------------
  * The paper notes that P degrades when Q varies strongly over the domain
  * (Sec. 3, remarks after Prop. 1).  A small network predicts a diagonal S from

@@ -117,6 +117,28 @@ class LShape:
         A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(self.N, self.N))
         return A.tocsr()
 
+    def matrix_rows(self, rows):
+        """Rows of A for a few global dofs (CSR, len(rows) x N) from the same
+        patch sums, without forming A: for large meshes."""
+        Mf, Kf = splines.univariate_matrices(self.knots, self.p, interior=False)
+        p, m = self.p, self.m
+        where = {int(g): [] for g in rows}
+        for k in (1, 2, 3):
+            bs, as_ = np.nonzero(np.isin(self.gid[k], list(where)))
+            for b, a in zip(bs, as_):
+                where[int(self.gid[k][b, a])].append((k, b, a))
+        ri, ci, vals = [], [], []
+        for j, g in enumerate(rows):
+            for k, b, a in where[int(g)]:
+                for bb in range(max(0, b - p), min(m, b + p + 1)):
+                    for aa in range(max(0, a - p), min(m, a + p + 1)):
+                        col = self.gid[k][bb, aa]
+                        if col >= 0:
+                            ri.append(j)
+                            ci.append(col)
+                            vals.append(Mf[b, bb] * Kf[a, aa] + Kf[b, bb] * Mf[a, aa])
+        return sp.csr_matrix((vals, (ri, ci)), shape=(len(rows), self.N))
+
     def load(self, f):
         """b_g = sum_k int_{Omega_k} f B_g dx by the (p+1)-point Gauss rule per
         element; dx = dxi / 4 on every patch."""
@@ -184,13 +206,19 @@ class Schwarz:
 
     def __init__(self, L: LShape, A=None):
         self.L = L
-        self.A = L.matrix() if A is None else A
+        self._A = A
         self.R, self.factors, self.lu = [], [], []
         for i in (1, 2):
             R, kn = L.subdomain(i)
             self.R.append(R)
             self.factors.append(fd.setup({"degree": L.p, "quad": L.p + 1, "knots": kn}))
             self.lu.append(None)
+
+    @property
+    def A(self):
+        if self._A is None:
+            self._A = self.L.matrix()
+        return self._A
 
     def ias(self, r):
         z = np.zeros_like(r)

@@ -75,6 +75,8 @@ _SIGNATURES = {
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
     "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "igafd_lshape_setup": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "igafd_lshape_corner": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
     "igafd_scaling_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
     "igafd_set_scaling_diag_ratio": (C.c_int, [C.c_void_p]),
     "igafd_mlp_num_params": (C.c_int, []),
@@ -219,6 +221,28 @@ def igafd_setup(problem: dict, stream=None) -> Context:
     _check(lib().igafd_setup(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
     n, N, nnz, bb = igafd_sizes(h)
     return Context(h, n, N, nnz, bb, d, pr.degree)
+
+
+def igafd_lshape_setup(knots, degree: int, stream=None) -> Context:
+    """L-shaped three-patch problem (C^0 interfaces) with the additive Schwarz
+    preconditioner P_IAS; every patch carries `knots` in both directions.
+    Vectors have the bounding square's N = n^2 entries; `ctx.hole` is the first
+    index of the entries that are not unknowns, `ctx.ndofs` the unknowns."""
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().igafd_lshape_setup(int(degree), len(k), k.ctypes.data_as(C.POINTER(C.c_double)),
+                                    stream if stream is not None else _current_stream(), C.byref(h)))
+    n, N, nnz, bb = igafd_sizes(h)
+    ctx = Context(h, n, N, nnz, bb, 2, int(degree))
+    ctx.hole, ctx.ndofs = igafd_lshape_corner(ctx)
+    return ctx
+
+
+def igafd_lshape_corner(ctx):
+    """(hole, ndofs): hole = -1 and ndofs = N for a single-patch context."""
+    hole, nd = C.c_int(), C.c_longlong()
+    _check(lib().igafd_lshape_corner(_h(ctx), C.byref(hole), C.byref(nd)))
+    return hole.value, nd.value
 
 
 def _h(ctx):

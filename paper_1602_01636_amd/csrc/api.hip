@@ -239,6 +239,34 @@ void free_dir(DevDir* d) {
   *d = DevDir{};
 }
 
+// Preconditioner-only context of one Schwarz subdomain (2D): the univariate
+// eigendecompositions of its two knot vectors and the FD intermediates; no A.
+igafd_status create_fd_sub(int p, const std::vector<double>& k1, const std::vector<double>& k2, hipStream_t st,
+                           igafd_ctx** out) {
+  std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(new igafd_ctx(), igafd_destroy);
+  c->dim = 2;
+  c->p = p;
+  c->stream = st;
+  c->N = 1;
+  const std::vector<double>* k[2] = {&k1, &k2};
+  igafd_status s;
+  for (int l = 0; l < 2; ++l) {
+    if ((s = build_direction(p, p + 1, (int)k[l]->size(), k[l]->data(), &c->dir[l])) != IGAFD_OK) return s;
+    c->n[l] = c->dir[l].n;
+    c->N *= c->n[l];
+    if ((s = upload_dir(c->dir[l], &c->ddir[l], st)) != IGAFD_OK) return s;
+  }
+  for (int b = 0; b < 2; ++b) IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[b], sizeof(double) * (size_t)c->N));
+  *out = c.release();
+  return IGAFD_OK;
+}
+
+bool is_lshape(const igafd_ctx* c, const char* what) {
+  if (c->hole < 0) return false;
+  set_error(std::string(what) + " is not defined for the L-shaped multi-patch context");
+  return true;
+}
+
 long long band_nnz(const igafd_ctx* c) {
   long long nnz = 1;
   for (int l = 0; l < c->dim; ++l) {
@@ -815,6 +843,7 @@ igafd_status igafd_univariate(int degree, int nknots, const double* knots, int q
 void igafd_destroy(igafd_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < 2; ++k) igafd_destroy(c->sub[k]);
   for (int l = 0; l < 3; ++l) free_dir(&c->ddir[l]);
   free_dev(c->band);
   free_dev(c->ext);
@@ -894,6 +923,62 @@ igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out)
   return IGAFD_OK;
 }
 
+igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, void* stream, igafd_ctx** out) {
+  if (!knots || !out) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  *out = nullptr;
+  const int p = degree;
+  Dir1D patch;
+  igafd_status s;
+  if ((s = build_direction(p, p + 1, nknots, knots, &patch)) != IGAFD_OK) return s;
+  // the knot vector of two patches side by side: the patch knots on [0,1/2]
+  // and on [1/2,1], joined by a knot of multiplicity p at 1/2 (C^0)
+  std::vector<double> kp(knots, knots + nknots), km;
+  km.assign(p + 1, 0.0);
+  for (int i = p + 1; i < nknots - p - 1; ++i) km.push_back(0.5 * knots[i]);
+  km.insert(km.end(), p, 0.5);
+  for (int i = p + 1; i < nknots - p - 1; ++i) km.push_back(0.5 + 0.5 * knots[i]);
+  km.insert(km.end(), p + 1, 1.0);
+  igafd_problem pr{};
+  pr.dim = 2;
+  pr.degree = p;
+  pr.nknots[0] = pr.nknots[1] = (int)km.size();
+  pr.knots[0] = pr.knots[1] = km.data();
+  pr.geom_kind = IGAFD_GEOM_IDENTITY;
+  pr.coef_kind = IGAFD_COEF_ONE;
+  pr.quad_per_dir = p + 1;
+  igafd_ctx* raw = nullptr;
+  if ((s = igafd_setup(&pr, stream, &raw)) != IGAFD_OK) return s;
+  std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(raw, igafd_destroy);
+  const int h = patch.n;
+  if (c->n[0] != 2 * h + 1 || c->n[1] != 2 * h + 1) {
+    set_error("internal: bounding-square grid does not match the patches");
+    return IGAFD_ERR_ARG;
+  }
+  // Theta_1 = the corner patch and the one above it: one patch along
+  // direction 1, two along direction 2; Theta_2 = the corner patch and the one
+  // to its right
+  if ((s = create_fd_sub(p, kp, km, c->stream, &c->sub[0])) != IGAFD_OK) return s;
+  if ((s = create_fd_sub(p, km, kp, c->stream, &c->sub[1])) != IGAFD_OK) return s;
+  c->hole = h;
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  *out = c.release();
+  return IGAFD_OK;
+}
+
+igafd_status igafd_lshape_corner(const igafd_ctx* c, int* hole, long long* ndofs) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  const long long w = c->hole >= 0 ? c->n[0] - c->hole : 0;
+  if (hole) *hole = c->hole;
+  if (ndofs) *ndofs = c->N - w * w;
+  return IGAFD_OK;
+}
+
 igafd_status igafd_sizes(const igafd_ctx* c, int n[3], long long* N, long long* nnz, long long* band_bytes) {
   if (!c) {
     set_error("null context");
@@ -912,7 +997,8 @@ igafd_status igafd_load_vector(igafd_ctx* c, int rhs_kind, double* b) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
   }
-  return assemble_load(c, rhs_kind, b);
+  const igafd_status s = assemble_load(c, rhs_kind, b);
+  return s == IGAFD_OK ? mask_hole(c, b) : s;
 }
 
 igafd_status igafd_apply_A(igafd_ctx* c, const double* x, double* y) {
@@ -940,6 +1026,7 @@ igafd_status igafd_set_scaling(igafd_ctx* c, const double* S) {
     c->scaling_set = false;
     return IGAFD_OK;
   }
+  if (is_lshape(c, "the scaled preconditioner")) return IGAFD_ERR_ARG;
   if (!c->scaling) IGAFD_HIP_CHECK(hipMalloc((void**)&c->scaling, sizeof(double) * c->N));
   IGAFD_HIP_CHECK(hipMemcpyAsync(c->scaling, S, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
   c->scaling_set = true;
@@ -951,6 +1038,7 @@ igafd_status igafd_diagonals(igafd_ctx* c, double* dA, double* dP) {
     set_error("null context");
     return IGAFD_ERR_ARG;
   }
+  if (is_lshape(c, "igafd_diagonals")) return IGAFD_ERR_ARG;
   return diagonals(c, dA, dP);
 }
 
@@ -959,6 +1047,7 @@ igafd_status igafd_features(igafd_ctx* c, float* feat) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
   }
+  if (is_lshape(c, "igafd_features")) return IGAFD_ERR_ARG;
   return features(c, feat);
 }
 
@@ -967,6 +1056,7 @@ igafd_status igafd_scaling_targets(igafd_ctx* c, float* t) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
   }
+  if (is_lshape(c, "igafd_scaling_targets")) return IGAFD_ERR_ARG;
   return scaling_targets(c, t);
 }
 
@@ -975,6 +1065,7 @@ igafd_status igafd_set_scaling_diag_ratio(igafd_ctx* c) {
     set_error("null context");
     return IGAFD_ERR_ARG;
   }
+  if (is_lshape(c, "the scaled preconditioner")) return IGAFD_ERR_ARG;
   if (!c->scaling) IGAFD_HIP_CHECK(hipMalloc((void**)&c->scaling, sizeof(double) * c->N));
   igafd_status st = diag_ratio_scaling(c, c->scaling);
   if (st == IGAFD_OK) c->scaling_set = true;
@@ -998,6 +1089,8 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
     set_error("batched solve needs count >= 1 contexts, vectors and options");
     return IGAFD_ERR_ARG;
   }
+  for (int i = 0; i < count; ++i)
+    if (ctxs[i] && is_lshape(ctxs[i], "igafd_solve_batched")) return IGAFD_ERR_ARG;
   return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
 }
 
@@ -1006,6 +1099,7 @@ igafd_status igafd_spectral_bounds(igafd_ctx* c, double* qmin, double* qmax) {
     set_error("null context");
     return IGAFD_ERR_ARG;
   }
+  if (is_lshape(c, "igafd_spectral_bounds")) return IGAFD_ERR_ARG;
   return spectral_bounds(c, qmin, qmax);
 }
 

@@ -23,6 +23,8 @@
 // Fused epilogues: scaling by the eigenvalue sums, the diagonal S of the
 // scaled preconditioner S P^-1 S on input and output, and the partial sums of
 // (r, s) for the CG recurrence.
+#include <algorithm>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -100,7 +102,8 @@ __device__ inline f4_t mfma<PBF16>(const short* a, const float* bf, const double
 }
 
 // D[k][c] = sum_i Wm[k][i] X(i, c) for k in this block's row range and the
-// wave's 16 columns.  TRX: X(i, c) = X[c * n + i] and D -> Y[c * n + k];
+// wave's 16 columns.  TRX: X(i, c) = X[c * ldx + i] and D -> Y[c * ldy + k]
+// (ldx = ldy = n for a whole grid; larger for a sub-block of a wider grid);
 // otherwise X(i, c) = X[b * bstride + i * C + c] and D -> Y[b * bstride + k * C + c].
 //
 // Block order: the nblk row blocks of one 64-column group run on the same XCD
@@ -109,7 +112,8 @@ __device__ inline f4_t mfma<PBF16>(const short* a, const float* bf, const double
 template <class Pr, int MT, bool TRX, typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout* __restrict__ Y,
                                                  const typename Pr::W* __restrict__ Wm, int npad, int n, int C,
-                                                 long long bstride, int nblk, int ncolblk, int ngroups, Epi ep) {
+                                                 long long bstride, int nblk, int ncolblk, int ngroups, Epi ep,
+                                                 int ldx, int ldy) {
   using acc_t = typename Pr::acc;
   constexpr int KS = Pr::KS, KPL = Pr::KPL;
   constexpr int UNR = 4;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout
           const int i = i0 + u * KS + grp * KPL + j;
           double v = 0.0;
           if (cok && i < n) {
-            const long long addr = TRX ? (long long)c * n + i : boff + (long long)i * C + c;
+            const long long addr = TRX ? (long long)c * ldx + i : boff + (long long)i * C + c;
             v = (double)X[addr];
             if (ep.flags & EPI_PRESCALE) v *= ep.S[addr];
           }
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(const Tin* __restrict__ X, Tout
       const int k = k0 + t * 16 + (Pr::ROW_STRIDE4 ? grp + 4 * r : grp * 4 + r);
       if (k < n && cok) {
         double v = (double)accv[t][r];
-        const long long addr = TRX ? (long long)c * n + k : boff + (long long)k * C + c;
+        const long long addr = TRX ? (long long)c * ldy + k : boff + (long long)k * C + c;
         if (ep.flags & EPI_LAMBDA) {
           const double ls = ep.dim == 3 ? ep.lamK[k] + ep.lam2[c / ep.n1] + ep.lam1[c % ep.n1]
                                         : ep.lamK[k] + ep.lam1[c];
@@ -216,15 +220,17 @@ int grid_x(int C, int B, int nblk) {
 
 template <class Pr, bool TRX, typename Tin, typename Tout>
 igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, const typename Pr::W* Wm, int npad, int n,
-                         int C, int B, long long bstride, const Epi& ep) {
+                         int C, int B, long long bstride, const Epi& ep, int ldx = 0, int ldy = 0) {
   const ModeShape ms = mode_shape(n, mt_max);
+  if (ldx <= 0) ldx = n;
+  if (ldy <= 0) ldy = n;
   const int ncolblk = (C + 63) / 64;
   const dim3 grid((unsigned)grid_x(C, B, ms.nblk), 1, 1);
   switch (ms.mt) {
 #define IGAFD_MT(M)                                                                                    \
   case M:                                                                                              \
     hipLaunchKernelGGL((k_mode<Pr, M, TRX, Tin, Tout>), grid, dim3(kBlock), 0, st, X, Y, Wm, npad, n, C, \
-                       bstride, ms.nblk, ncolblk, B * ncolblk, ep);                                    \
+                       bstride, ms.nblk, ncolblk, B * ncolblk, ep, ldx, ldy);                          \
     break;
     IGAFD_MT(1) IGAFD_MT(2) IGAFD_MT(3) IGAFD_MT(4) IGAFD_MT(5) IGAFD_MT(6) IGAFD_MT(7) IGAFD_MT(8)
 #undef IGAFD_MT
@@ -688,8 +694,11 @@ int dot_blocks_for(const igafd_ctx* c) {
 }
 
 // T: intermediate type (double for FP64, float otherwise)
+// ldr, lds (2D): row strides of r and s when they are sub-blocks of a wider
+// grid (0: n1)
 template <class Pr, typename T>
-igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, double* partial, const int* flag) {
+igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, double* partial, const int* flag,
+                   int ldr = 0, int lds = 0) {
   const DevDir* d = c->ddir;
   const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
   T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
@@ -735,25 +744,108 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
                                              (long long)n1 * n2, e0)));
     IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
   } else {
-    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in)));
+    IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in,
+                                                 ldr, n1)));
     e_lam.lamK = d[1].lam;
     IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, 1, 0, e_lam)));
     IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b1, b0, wmat<Pr>(d[1], 1), d[1].npad, n2, n1, 1, 0, e0)));
-    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2, 1, 0, e_out)));
+    IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2, 1, 0, e_out,
+                                                 n1, lds)));
   }
 #undef IGAFD_TRY
   return IGAFD_OK;
+}
+
+// ------------------------------------------------------------------------
+// Overlapping additive Schwarz on the L-shaped three-patch domain (Sec. 6
+// eq. Pias with the local approximations P_i):
+//   s = R_1^T P_1^-1 R_1 r + R_2^T P_2^-1 R_2 r.
+// Vectors use the bounding square's n x n grid (direction 1 fastest) with the
+// removed quarter i1, i2 >= h held at zero.  The subdomains are tensor
+// sub-blocks of that grid:
+//   Theta_2 = rows i2 < h (all i1): contiguous, an n x h grid;
+//   Theta_1 = columns i1 < h of every row: an h x n grid of row stride n.
+// P_2^-1 R_2 r is written straight into the first h rows of s, P_1^-1 R_1 r
+// into t (h x n, contiguous); the combine pass adds them, zeroes the removed
+// quarter and forms the (r, s) block partials.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_schwarz_combine(const double* __restrict__ t, double* __restrict__ s,
+                                                            const double* __restrict__ r, int n, int h, long long N,
+                                                            double* __restrict__ partial, const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (i < N) {
+    const int i1 = (int)(i % n), i2 = (int)(i / n);
+    double v = i2 < h ? s[i] : 0.0;
+    if (i1 < h) v += t[(long long)i2 * h + i1];
+    s[i] = v;
+    dot = r[i] * v;
+  }
+  if (partial) {
+    const double sum = block_sum(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+  }
+}
+
+int schwarz_blocks(const igafd_ctx* c) { return (int)((c->N + kBlock - 1) / kBlock); }
+
+template <class Pr, typename T>
+igafd_status schwarz(igafd_ctx* c, const double* r, double* s, double* partial, const int* flag) {
+  igafd_ctx* s1 = c->sub[0];
+  igafd_ctx* s2 = c->sub[1];
+  const int n = c->n[0], h = c->hole;
+  if (!s1 || !s2 || c->dim != 2 || c->n[1] != n || s1->n[0] != h || s1->n[1] != n || s2->n[0] != n ||
+      s2->n[1] != h) {
+    set_error("internal: Schwarz subdomains do not match the L-shaped grid");
+    return IGAFD_ERR_ARG;
+  }
+  if (partial && schwarz_blocks(c) > c->npartial) {
+    set_error("internal: Schwarz grid larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
+  s1->fd_tiles = s2->fd_tiles = c->fd_tiles;
+  igafd_status st = apply<Pr, T>(s2, r, s, nullptr, nullptr, flag, n, n);
+  if (st != IGAFD_OK) return st;
+  st = apply<Pr, T>(s1, r, c->fdbuf[0], nullptr, nullptr, flag, n, h);
+  if (st != IGAFD_OK) return st;
+  hipLaunchKernelGGL(k_schwarz_combine, dim3((unsigned)schwarz_blocks(c)), dim3(kBlock), 0, c->stream, c->fdbuf[0], s,
+                     r, n, h, c->N, partial, flag);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+igafd_status schwarz_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
+                           const int* flag) {
+  if (S) {
+    set_error("the scaled preconditioner is not defined for the L-shaped multi-patch problem");
+    return IGAFD_ERR_ARG;
+  }
+  switch (prec) {
+    case IGAFD_FP64:
+      return schwarz<PF64, double>(c, r, s, partial, flag);
+    case IGAFD_FP32:
+      return schwarz<PF32, float>(c, r, s, partial, flag);
+    case IGAFD_BF16:
+      return schwarz<PBF16, float>(c, r, s, partial, flag);
+    default:
+      set_error("unknown precision");
+      return IGAFD_ERR_ARG;
+  }
 }
 
 }  // namespace
 
 bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c); }
 
-int fd_dot_blocks(const igafd_ctx* c) { return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c); }
+int fd_dot_blocks(const igafd_ctx* c) {
+  if (c->hole >= 0) return schwarz_blocks(c);
+  return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c);
+}
 
 int fd_dot_blocks_max(const igafd_ctx* c) {
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
-  int m = slice_blocks(c);
+  int m = std::max(slice_blocks(c), schwarz_blocks(c));
   for (int t = 1; t <= 8; ++t) {
     const int g = grid_x(C, 1, mode_shape(c->n[0], t).nblk);
     if (g > m) m = g;
@@ -763,6 +855,7 @@ int fd_dot_blocks_max(const igafd_ctx* c) {
 
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
                       const int* flag) {
+  if (c->hole >= 0) return schwarz_apply(c, prec, r, s, S, partial, flag);
   if (c->fd_fused && fused_ok(c)) {
     const DevDir* d = c->ddir;
     switch (prec) {

@@ -101,6 +101,11 @@ struct igafd_ctx {
   long long ext_cap = 0;                   // doubles allocated at ext
   int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
   int fd_fused = 1;                        // 3D: three fused passes instead of six products
+  // L-shaped multi-patch context: the grid is the bounding square's, the
+  // quarter i1 >= hole && i2 >= hole is not part of the domain (held at zero);
+  // sub[0], sub[1]: preconditioner-only contexts of the two Schwarz subdomains
+  int hole = -1;
+  igafd_ctx* sub[2] = {nullptr, nullptr};
   // workspace
   double *r = nullptr, *z = nullptr, *q = nullptr, *zold = nullptr;
   double* pv_pad = nullptr;                // search direction with the band's zero halo
@@ -132,6 +137,7 @@ igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* par
 int spmv_blocks(const igafd_ctx* c);
 bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3);
 igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3);
+igafd_status mask_hole(igafd_ctx* c, double* y);
 // fd.hip
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                       double* partial_rz, const int* flag);

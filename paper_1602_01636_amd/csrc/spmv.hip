@@ -55,7 +55,7 @@ template <int D, int P, int R>
 __global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band, long long Ns,
                                                  const double* __restrict__ x, double* __restrict__ y, int n1, int n2,
                                                  long long N, double* __restrict__ partial,
-                                                 const int* __restrict__ flag) {
+                                                 const int* __restrict__ flag, int hole) {
   if (flag && *flag) return;  // CG already stopped: iteration enqueued ahead is a no-op
   constexpr int W = 2 * P + 1;
   constexpr int NPAIR = (D == 3) ? W * W : W;
@@ -63,18 +63,35 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band
   const long long i0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * R;
   double dot = 0.0;
   if (i0 < N) {
+    // rows of the removed quarter of an L-shaped domain (2D, hole >= 0) are
+    // not unknowns: written as zero, computed only when the thread also owns
+    // a row of the domain
+    bool out[R];
+    bool all_out = hole >= 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      out[r] = false;
+      if (hole >= 0) {
+        const long long i = i0 + r;
+        out[r] = i % n1 >= hole && i / n1 >= hole;
+        all_out = all_out && out[r];
+      }
+    }
     const long long s2 = n1, s3 = (long long)n1 * n2;
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int o32 = 0; o32 < MID; ++o32) pair_step<D, P, R, 0>(o32, band, Ns, x, i0, s2, s3, acc);
-    pair_step<D, P, R, 1>(MID, band, Ns, x, i0, s2, s3, acc);
-    for (int o32 = MID + 1; o32 < NPAIR; ++o32) pair_step<D, P, R, 2>(o32, band, Ns, x, i0, s2, s3, acc);
+    if (!all_out) {
+      for (int o32 = 0; o32 < MID; ++o32) pair_step<D, P, R, 0>(o32, band, Ns, x, i0, s2, s3, acc);
+      pair_step<D, P, R, 1>(MID, band, Ns, x, i0, s2, s3, acc);
+      for (int o32 = MID + 1; o32 < NPAIR; ++o32) pair_step<D, P, R, 2>(o32, band, Ns, x, i0, s2, s3, acc);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (i0 + r < N) {
-        y[i0 + r] = acc[r];
-        dot += x[i0 + r] * acc[r];
+        const double v = out[r] ? 0.0 : acc[r];
+        y[i0 + r] = v;
+        dot += x[i0 + r] * v;
       }
   }
   if (partial) {
@@ -83,10 +100,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band
   }
 }
 
-// copy a vector into the interior of a zero-halo buffer
-__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long N) {
+// copy a vector into the interior of a zero-halo buffer; entries of the
+// removed quarter of an L-shaped domain (hole >= 0) become zero
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long N, int n1, int hole) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < N) dst[i] = src[i];
+  if (i < N) dst[i] = (hole >= 0 && i % n1 >= hole && i / n1 >= hole) ? 0.0 : src[i];
+}
+
+// zero the removed quarter i1, i2 >= hole of an n1 x n1 grid in place
+__global__ void k_zero_hole(double* __restrict__ y, int n1, int hole) {
+  const int w = n1 - hole;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < (long long)w * w) y[(long long)(hole + i / w) * n1 + hole + i % w] = 0.0;
 }
 
 // ------------------------------------------------------------------------
@@ -326,7 +351,7 @@ igafd_status launch(igafd_ctx* c, const double* xpad, double* y, double* partial
     return IGAFD_ERR_ARG;
   }
   hipLaunchKernelGGL((k_spmv<D, P, R>), dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, c->Ns, xpad, y,
-                     c->n[0], c->n[1], c->N, partial, flag);
+                     c->n[0], c->n[1], c->N, partial, flag, c->dim == 2 ? c->hole : -1);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
@@ -537,9 +562,20 @@ igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, 
 // zero-halo buffer.
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag) {
   const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, c->stream, x, c->xpad + c->halo, c->N);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, c->stream, x, c->xpad + c->halo, c->N, c->n[0],
+                     c->dim == 2 ? c->hole : -1);
   IGAFD_HIP_CHECK(hipGetLastError());
   return spmv(c, c->xpad + c->halo, y, partial, flag);
+}
+
+igafd_status mask_hole(igafd_ctx* c, double* y) {
+  if (c->hole < 0 || c->dim != 2) return IGAFD_OK;
+  const long long w = c->n[0] - c->hole;
+  if (w <= 0) return IGAFD_OK;
+  hipLaunchKernelGGL(k_zero_hole, dim3((unsigned)((w * w + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, y,
+                     c->n[0], c->hole);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
 }
 
 }  // namespace igafd

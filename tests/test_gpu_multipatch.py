@@ -1,0 +1,169 @@
+"""GPU parity of the L-shaped multi-patch problem (Sec. 6 eq. Pias, Sec. 7
+multi-patch experiment) against the oracle's glued three-patch system.
+
+The library keeps vectors on the bounding square's grid; the oracle numbers
+the glued global functions.  `LShape.square_index` maps one to the other, so
+every comparison is element by element over the unknowns, and the entries
+that are not unknowns must come back as exact zeros (whatever the inputs hold
+there).  Tolerances follow the single-patch tests: A x 1e-12 relative to
+sum_j |a_ij x_j| per row; P_IAS^-1 r FP64 1e-11, FP32 1e-4, BF16 5e-2; the
+load vector 1e-13; solutions at rtol 1e-8 within 1e-7 of the oracle's.
+
+Cases: the smallest mesh (one interior function per patch and direction),
+uniform and jittered knots, p = 1..5, sizes spanning several 16-row mode
+tiles with ragged tails and several 256-row blocks.
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import rel, to_dev, to_host
+from oracle import multipatch as mp
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("single_interior_p2", synth.uniform_knots(1, 2), 2),
+    ("uniform_p2", synth.uniform_knots(5, 2), 2),
+    ("uniform_p1", synth.uniform_knots(40, 1), 1),
+    ("uniform_p3", synth.uniform_knots(24, 3), 3),
+    ("jittered_p4", synth.jittered_knots(17, 4, 9), 4),
+    ("uniform_p5", synth.uniform_knots(9, 5), 5),
+]
+IDS = [c[0] for c in CASES]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import paper_1602_01636_amd as api
+    api.lib()
+    return api
+
+
+_cache = {}
+
+
+def setup_case(api, name, knots, p):
+    if name not in _cache:
+        L = mp.LShape(knots, p)
+        S = mp.Schwarz(L)
+        pos, n = L.square_index()
+        _cache[name] = (L, S, pos, n)
+    L, S, pos, n = _cache[name]
+    ctx = api.igafd_lshape_setup(knots, p)
+    return ctx, L, S, pos, n
+
+
+def outside(pos, n):
+    mask = np.ones(n * n, dtype=bool)
+    mask[pos] = False
+    return mask
+
+
+@pytest.mark.parametrize("name,knots,p", CASES, ids=IDS)
+def test_lshape_layout(api, name, knots, p):
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        assert ctx.hole == L.m - 2 and ctx.n[:2] == [n, n] and ctx.N == n * n
+        assert ctx.ndofs == L.N
+        # the grid entries that are not unknowns form the quarter i1, i2 >= hole
+        i1, i2 = np.arange(n * n) % n, np.arange(n * n) // n
+        assert np.array_equal(outside(pos, n), (i1 >= ctx.hole) & (i2 >= ctx.hole))
+
+
+@pytest.mark.parametrize("name,knots,p", CASES, ids=IDS)
+def test_lshape_apply_A(api, name, knots, p):
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        A = S.A
+        x = synth.random_vector(n * n, 31)          # nonzero also where there are no unknowns
+        y = to_dev(np.zeros(n * n))
+        api.igafd_apply_A(ctx, to_dev(x), y)
+        yg = to_host(y)
+        ref = A @ x[pos]
+        scale = abs(A) @ np.abs(x[pos])
+        assert np.max(np.abs(yg[pos] - ref) / scale) < 1e-12
+        assert np.all(yg[outside(pos, n)] == 0.0)
+
+
+@pytest.mark.parametrize("name,knots,p", CASES, ids=IDS)
+def test_lshape_schwarz_apply(api, name, knots, p):
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        r = synth.random_vector(n * n, 32)
+        ref = S.ias(r[pos])
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2)):
+            s = to_dev(np.full(n * n, 7.0))          # stale values must be overwritten
+            api.igafd_apply_precond(ctx, prec, to_dev(r), s)
+            sg = to_host(s)
+            assert rel(sg[pos], ref) < tol, prec
+            assert np.all(sg[outside(pos, n)] == 0.0), prec
+
+
+@pytest.mark.parametrize("name,knots,p", CASES, ids=IDS)
+def test_lshape_load_vector(api, name, knots, p):
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        for f in (synth.RHS_PAPER_POLY, {"kind": "one"}, synth.RHS_SINPROD):
+            b = to_dev(np.zeros(n * n))
+            api.igafd_load_vector(ctx, f, b)
+            bg = to_host(b)
+            assert rel(bg[pos], L.load(f)) < 1e-13, f
+            assert np.all(bg[outside(pos, n)] == 0.0)
+
+
+@pytest.mark.parametrize("name,knots,p", CASES[1:], ids=IDS[1:])
+def test_lshape_solve(api, name, knots, p):
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        b = L.load(synth.RHS_PAPER_POLY)
+        u_or, info_or = S.solve(b, "ias")
+        bs = np.zeros(n * n)
+        bs[pos] = b
+        u = to_dev(np.zeros(n * n))
+        info = api.igafd_solve(ctx, to_dev(bs), u, rtol=1e-8)
+        ug = to_host(u)
+        assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+        assert abs(info["iters"] - info_or["iters"]) <= 1, (info["iters"], info_or["iters"])
+        assert rel(ug[pos], u_or) <= 1e-7
+        assert np.all(ug[outside(pos, n)] == 0.0)
+        # mixed-precision local solves in flexible CG
+        for prec in ("fp32", "bf16"):
+            u2 = to_dev(np.zeros(n * n))
+            info2 = api.igafd_solve(ctx, to_dev(bs), u2, rtol=1e-8, precision=prec)
+            assert info2["true_relres"] <= 1e-8, prec
+            assert info2["iters"] <= info_or["iters"] + (2 if prec == "fp32" else 6), prec
+            assert rel(to_host(u2)[pos], u_or) <= 1e-6, prec
+
+
+def test_lshape_autotune_keeps_results(api):
+    name, knots, p = CASES[3]
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        r = to_dev(synth.random_vector(n * n, 33))
+        s0, s1, y0, y1 = (to_dev(np.zeros(n * n)) for _ in range(4))
+        api.igafd_apply_precond(ctx, "fp64", r, s0)
+        api.igafd_apply_A(ctx, r, y0)
+        api.igafd_autotune(ctx)
+        api.igafd_apply_precond(ctx, "fp64", r, s1)
+        api.igafd_apply_A(ctx, r, y1)
+        assert rel(to_host(s1), to_host(s0)) < 1e-13
+        assert rel(to_host(y1), to_host(y0)) < 1e-14
+
+
+def test_lshape_rejects_single_patch_only_calls(api):
+    name, knots, p = CASES[1]
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        v = to_dev(np.ones(n * n))
+        with pytest.raises(api.IgafdError):
+            api.igafd_set_scaling(ctx, v)
+        with pytest.raises(api.IgafdError):
+            api.igafd_diagonals(ctx, v, None)
+        with pytest.raises(api.IgafdError):
+            api.igafd_spectral_bounds(ctx)
+        with pytest.raises(api.IgafdError):
+            api.igafd_solve_batched([ctx], [v], [to_dev(np.zeros(n * n))])
+        # a single-patch context reports no removed quarter
+        with api.igafd_setup(synth.square_2d(E=6, p=2)) as c2:
+            assert api.igafd_lshape_corner(c2) == (-1, c2.N)

@@ -53,6 +53,13 @@ def test_glued_matrix_equals_single_patch_assembly(E, p, seed):
     assert L.N + (n - c) ** 2 == n * n
 
 
+def test_matrix_rows_match_matrix():
+    L = lshape(5, 3, 4)
+    A = L.matrix().toarray()
+    rows = np.array([0, 3, L.N // 3, L.N // 2, L.N - 1])
+    assert np.abs(L.matrix_rows(rows).toarray() - A[rows]).max() <= 1e-15 * np.abs(A).max() * 10
+
+
 def _patch_values(L, k, x, y, u):
     """Value at parameter points (x[i], y[i]) of patch k of the global function u."""
     Bx = splines.basis(L.knots, L.p, x)
