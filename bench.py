@@ -18,6 +18,8 @@ Other workloads (--workload), each printing one JSON line of the same form:
   learned  learned diagonal scaling: trained on 2000 small warped cubes, evaluated on the
            p = 4, 112^3 warped cube: plain P, learned S P^-1 S, exact diagonal-ratio S
   square   2D unit square, identity map, p = 3, 64^2 elements (one iteration: launch latency)
+  lshape   L-shaped domain of three square patches with C0 interfaces (Sec. 6, Table L),
+           h^-1 = 1024 elements per patch and direction, p = 3: CG + additive Schwarz P_IAS
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -400,12 +402,111 @@ def run_square(args, api, torch, synth):
     return out
 
 
+def lshape_nnz(n, hole, p):
+    """Stored nonzeros of A over the unknowns of the L-shaped grid: pairs of
+    unknowns whose indices differ by at most p in both directions."""
+    mask = np.ones((n, n), dtype=bool)
+    mask[hole:, hole:] = False
+    pad = np.pad(mask, p)
+    cnt = np.zeros((n, n), dtype=np.int64)
+    for o2 in range(2 * p + 1):
+        for o1 in range(2 * p + 1):
+            cnt += pad[o2:o2 + n, o1:o1 + n]
+    return int(cnt[mask].sum())
+
+
+def lshape_cpu_baseline(target_iters, E_full, p, flops_iter_full):
+    """The oracle's CG + P_IAS (glued three-patch matrix, FD local solves) on
+    a bounded sample: h^-1 = 128, same p; time per iteration scaled by the
+    FLOPs per iteration (A product 2 nnz, P_IAS 8 h n (h + n)) to the full
+    mesh, times the GPU's iteration count."""
+    import synth
+    from oracle import multipatch as mp
+    E = 128
+    L = mp.LShape(synth.uniform_knots(E, p), p)
+    S = mp.Schwarz(L)
+    A = S.A
+    b = L.load(synth.RHS_PAPER_POLY)
+    t0 = time.perf_counter()
+    reps = iters = 0
+    while time.perf_counter() - t0 < 10.0 or reps < 3:
+        _, info = S.solve(b, "ias")
+        iters += info["iters"]
+        reps += 1
+    dt = time.perf_counter() - t0
+    h = L.m - 2
+    n = 2 * h + 1
+    per_iter = dt / iters
+    flops_s = 2 * A.nnz + 8 * h * n * (h + n)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": per_iter * flops_iter_full / flops_s * target_iters, "unit": "s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"oracle CG + P_IAS on the L-shaped domain at h^-1={E} p={p} (N={L.N}), {reps} solves, "
+                      f"{per_iter * 1e3:.2f} ms/iteration, scaled by FLOPs/iteration to h^-1={E_full} "
+                      f"and x {target_iters} iterations",
+            "sample_s_per_iter": per_iter}
+
+
+def run_lshape(args, api, torch, synth):
+    E, p = args.elements or 1024, args.degree or 3
+    knots = synth.uniform_knots(E, p)
+    t0 = time.perf_counter()
+    ctx = api.igafd_lshape_setup(knots, p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    n, h = ctx.n[0], ctx.hole
+    b = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
+    api.igafd_load_vector(ctx, synth.RHS_PAPER_POLY, b)
+    u = torch.zeros_like(b)
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup)
+    ms_per_step = 1e3 * float(np.median(times))
+    variants = {}
+    if not args.no_variants:
+        for prec in ("fp32", "bf16"):
+            tv, iv = timed_solves(api, torch, ctx, b, u, 3, 1, precision=prec)
+            variants[prec] = {"ms": 1e3 * float(np.median(tv)), "iters": iv[-1]["iters"],
+                              "true_relres": iv[-1]["true_relres"]}
+    x = torch.randn(ctx.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), 20)
+    t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, x, y), 10)
+            for pr in ("fp64", "fp32", "bf16")}
+    nnz_L = lshape_nnz(n, h, p)
+    by = 8 * ((nnz_L + ctx.ndofs) // 2) + 16 * ctx.ndofs
+    fl = 8 * h * n * (h + n)
+    log(f"A product {t_spmv * 1e3:.1f} us ({by / t_spmv / 1e6:.0f} GB/s); P_IAS " +
+        " ".join(f"{pr} {t * 1e3:.1f} us ({fl / t / 1e9:.1f} TF/s)" for pr, t in t_fd.items()))
+    tf = fl / t_fd["fp64"] / 1e9
+    roof = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TF, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TF,
+            "traffic": None, "kernel": "P_IAS apply: two subdomain FD applies (FP64 mode products) + combine",
+            "algorithmic_flops": fl}
+    spmv_roof = {"bound": "hbm", "achieved": by / t_spmv / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": by / t_spmv / 1e6 / HBM_PEAK_GBS, "algorithmic_bytes": by}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = lshape_cpu_baseline(infos[-1]["iters"], E, p, 2 * nnz_L + fl)
+    workload = {"workload": f"L-shaped domain, 3 square patches with C0 interfaces, h^-1={E} per patch, p={p}, "
+                            f"{ctx.ndofs} unknowns (grid {n}^2), f = 2 sum(x_i^2 - x_i), CG + additive Schwarz "
+                            f"P_IAS with FP64 FD local solves", "elements_per_patch": E, "degree": p,
+                "unknowns": ctx.ndofs}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"], "setup_s": t_setup,
+        "variants": variants, "kernel_ms": {"spmv": t_spmv, **{f"schwarz_{pr}": t for pr, t in t_fd.items()}},
+        "roofline": roof, "spmv_roofline": spmv_roof, "cpu_baseline": cpu})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square"])
+    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape"])
     ap.add_argument("--elements", type=int, default=0)
     ap.add_argument("--degree", type=int, default=0)
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
@@ -426,7 +527,7 @@ def main():
 
     torch.cuda.set_device(0)
     run = {"ring": run_ring, "warped": run_warped, "batch": run_batch, "learned": run_learned,
-           "square": run_square}[args.workload]
+           "square": run_square, "lshape": run_lshape}[args.workload]
     out = run(args, api, torch, synth)
     print(json.dumps(out), flush=True)
 

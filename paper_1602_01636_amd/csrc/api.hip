@@ -192,8 +192,19 @@ igafd_status upload_dir(const Dir1D& h, DevDir* d, hipStream_t st) {
   if ((s = dev_upload(&d->qw, h.qw.data(), h.qw.size(), st)) != IGAFD_OK) return s;
   if ((s = dev_upload(&d->val, h.val.data(), h.val.size(), st)) != IGAFD_OK) return s;
   if ((s = dev_upload(&d->der, h.der.data(), h.der.size(), st)) != IGAFD_OK) return s;
-  if ((s = dev_upload(&d->lam, h.lam.data(), h.lam.size(), st)) != IGAFD_OK) return s;
   const int n = h.n, np = d->npad;
+  if (h.U.empty()) {  // no eigendecomposition: element tables and diagonals only
+    std::vector<double> dm(n), dk(n);
+    for (int i = 0; i < n; ++i) {
+      dm[i] = h.M[(size_t)i * n + i];
+      dk[i] = h.K[(size_t)i * n + i];
+    }
+    if ((s = dev_upload(&d->diagM, dm.data(), dm.size(), st)) != IGAFD_OK) return s;
+    if ((s = dev_upload(&d->diagK, dk.data(), dk.size(), st)) != IGAFD_OK) return s;
+    IGAFD_HIP_CHECK(hipStreamSynchronize(st));
+    return IGAFD_OK;
+  }
+  if ((s = dev_upload(&d->lam, h.lam.data(), h.lam.size(), st)) != IGAFD_OK) return s;
   std::vector<double> w64((size_t)np * np);
   std::vector<float> w32((size_t)np * np);
   std::vector<uint16_t> wbf((size_t)np * np);
@@ -241,17 +252,16 @@ void free_dir(DevDir* d) {
 
 // Preconditioner-only context of one Schwarz subdomain (2D): the univariate
 // eigendecompositions of its two knot vectors and the FD intermediates; no A.
-igafd_status create_fd_sub(int p, const std::vector<double>& k1, const std::vector<double>& k2, hipStream_t st,
-                           igafd_ctx** out) {
+igafd_status create_fd_sub(int p, const Dir1D& d1, const Dir1D& d2, hipStream_t st, igafd_ctx** out) {
   std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(new igafd_ctx(), igafd_destroy);
   c->dim = 2;
   c->p = p;
   c->stream = st;
   c->N = 1;
-  const std::vector<double>* k[2] = {&k1, &k2};
+  c->dir[0] = d1;
+  c->dir[1] = d2;
   igafd_status s;
   for (int l = 0; l < 2; ++l) {
-    if ((s = build_direction(p, p + 1, (int)k[l]->size(), k[l]->data(), &c->dir[l])) != IGAFD_OK) return s;
     c->n[l] = c->dir[l].n;
     c->N *= c->n[l];
     if ((s = upload_dir(c->dir[l], &c->ddir[l], st)) != IGAFD_OK) return s;
@@ -822,6 +832,70 @@ igafd_status autotune_impl(igafd_ctx* c, int reps) {
 
 using namespace igafd;
 
+namespace igafd {
+namespace {
+// fd = false: no univariate eigendecompositions (a context whose
+// preconditioner is applied by other contexts)
+igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, bool fd) {
+  if (!pr || !out) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  *out = nullptr;
+  if (pr->dim != 2 && pr->dim != 3) {
+    set_error("dim must be 2 or 3");
+    return IGAFD_ERR_ARG;
+  }
+  std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(new igafd_ctx(), igafd_destroy);
+  c->dim = pr->dim;
+  c->p = pr->degree;
+  c->stream = (hipStream_t)stream;
+  const int q = pr->quad_per_dir > 0 ? pr->quad_per_dir : pr->degree + 1;
+  igafd_status s;
+  if ((s = parse_geometry(pr, &c->geom)) != IGAFD_OK) return s;
+  c->N = 1;
+  for (int l = 0; l < pr->dim; ++l) {
+    if ((s = build_direction(pr->degree, q, pr->nknots[l], pr->knots[l], &c->dir[l], fd)) != IGAFD_OK) return s;
+    c->n[l] = c->dir[l].n;
+    c->N *= c->n[l];
+  }
+  for (int l = 0; l < pr->dim; ++l)
+    if ((s = upload_dir(c->dir[l], &c->ddir[l], c->stream)) != IGAFD_OK) return s;
+  const int W = 2 * c->p + 1;
+  const int Sz = (c->dim == 3) ? W * W * W : W * W;
+  c->H = (Sz + 1) / 2;
+  // zero halo: the largest stencil offset, rounded to 64 rows
+  const long long maxoff = (long long)c->p * (1 + c->n[0] + (c->dim == 3 ? (long long)c->n[0] * c->n[1] : 0));
+  c->halo = (maxoff + 63) / 64 * 64;
+  c->Ns = (c->N + 2 * c->halo + 8 + 63) / 64 * 64;
+  c->nnz = band_nnz(c.get());
+  if (const char* e = std::getenv("IGAFD_SPMV_ROWS")) c->spmv_rows = std::atoi(e);
+  if (const char* e = std::getenv("IGAFD_FD_TILES")) c->fd_tiles = std::atoi(e);
+  if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
+  if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
+  if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
+  {
+    // 3D: tiled A product by default (IGAFD_SPMV_TILE=0 selects the row-parallel
+    // kernel, IGAFD_SPMV_TILE=<b2>x<b3> a tile shape)
+    int b2 = 0, b3 = 0;
+    const char* e = std::getenv("IGAFD_SPMV_TILE");
+    if (e && std::strchr(e, 'x')) {
+      b2 = std::atoi(e);
+      b3 = std::atoi(std::strchr(e, 'x') + 1);
+    } else if (!(e && std::atoi(e) == 0) && !spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
+      b2 = b3 = 0;
+    }
+    if ((s = spmv_set_tile(c.get(), b2, b3)) != IGAFD_OK) return s;
+  }
+  if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
+  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  *out = c.release();
+  return IGAFD_OK;
+}
+}  // namespace
+}  // namespace igafd
+
 extern "C" {
 
 const char* igafd_last_error(void) { return g_err.c_str(); }
@@ -865,62 +939,9 @@ void igafd_destroy(igafd_ctx* c) {
   delete c;
 }
 
+
 igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out) {
-  if (!pr || !out) {
-    set_error("null argument");
-    return IGAFD_ERR_ARG;
-  }
-  *out = nullptr;
-  if (pr->dim != 2 && pr->dim != 3) {
-    set_error("dim must be 2 or 3");
-    return IGAFD_ERR_ARG;
-  }
-  std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(new igafd_ctx(), igafd_destroy);
-  c->dim = pr->dim;
-  c->p = pr->degree;
-  c->stream = (hipStream_t)stream;
-  const int q = pr->quad_per_dir > 0 ? pr->quad_per_dir : pr->degree + 1;
-  igafd_status s;
-  if ((s = parse_geometry(pr, &c->geom)) != IGAFD_OK) return s;
-  c->N = 1;
-  for (int l = 0; l < pr->dim; ++l) {
-    if ((s = build_direction(pr->degree, q, pr->nknots[l], pr->knots[l], &c->dir[l])) != IGAFD_OK) return s;
-    c->n[l] = c->dir[l].n;
-    c->N *= c->n[l];
-  }
-  for (int l = 0; l < pr->dim; ++l)
-    if ((s = upload_dir(c->dir[l], &c->ddir[l], c->stream)) != IGAFD_OK) return s;
-  const int W = 2 * c->p + 1;
-  const int Sz = (c->dim == 3) ? W * W * W : W * W;
-  c->H = (Sz + 1) / 2;
-  // zero halo: the largest stencil offset, rounded to 64 rows
-  const long long maxoff = (long long)c->p * (1 + c->n[0] + (c->dim == 3 ? (long long)c->n[0] * c->n[1] : 0));
-  c->halo = (maxoff + 63) / 64 * 64;
-  c->Ns = (c->N + 2 * c->halo + 8 + 63) / 64 * 64;
-  c->nnz = band_nnz(c.get());
-  if (const char* e = std::getenv("IGAFD_SPMV_ROWS")) c->spmv_rows = std::atoi(e);
-  if (const char* e = std::getenv("IGAFD_FD_TILES")) c->fd_tiles = std::atoi(e);
-  if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
-  if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
-  IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
-  if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
-  {
-    // 3D: tiled A product by default (IGAFD_SPMV_TILE=0 selects the row-parallel
-    // kernel, IGAFD_SPMV_TILE=<b2>x<b3> a tile shape)
-    int b2 = 0, b3 = 0;
-    const char* e = std::getenv("IGAFD_SPMV_TILE");
-    if (e && std::strchr(e, 'x')) {
-      b2 = std::atoi(e);
-      b3 = std::atoi(std::strchr(e, 'x') + 1);
-    } else if (!(e && std::atoi(e) == 0) && !spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
-      b2 = b3 = 0;
-    }
-    if ((s = spmv_set_tile(c.get(), b2, b3)) != IGAFD_OK) return s;
-  }
-  if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
-  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
-  *out = c.release();
-  return IGAFD_OK;
+  return setup_impl(pr, stream, out, true);
 }
 
 igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, void* stream, igafd_ctx** out) {
@@ -935,7 +956,7 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   if ((s = build_direction(p, p + 1, nknots, knots, &patch)) != IGAFD_OK) return s;
   // the knot vector of two patches side by side: the patch knots on [0,1/2]
   // and on [1/2,1], joined by a knot of multiplicity p at 1/2 (C^0)
-  std::vector<double> kp(knots, knots + nknots), km;
+  std::vector<double> km;
   km.assign(p + 1, 0.0);
   for (int i = p + 1; i < nknots - p - 1; ++i) km.push_back(0.5 * knots[i]);
   km.insert(km.end(), p, 0.5);
@@ -950,7 +971,7 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   pr.coef_kind = IGAFD_COEF_ONE;
   pr.quad_per_dir = p + 1;
   igafd_ctx* raw = nullptr;
-  if ((s = igafd_setup(&pr, stream, &raw)) != IGAFD_OK) return s;
+  if ((s = setup_impl(&pr, stream, &raw, false)) != IGAFD_OK) return s;
   std::unique_ptr<igafd_ctx, void (*)(igafd_ctx*)> c(raw, igafd_destroy);
   const int h = patch.n;
   if (c->n[0] != 2 * h + 1 || c->n[1] != 2 * h + 1) {
@@ -960,8 +981,10 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   // Theta_1 = the corner patch and the one above it: one patch along
   // direction 1, two along direction 2; Theta_2 = the corner patch and the one
   // to its right
-  if ((s = create_fd_sub(p, kp, km, c->stream, &c->sub[0])) != IGAFD_OK) return s;
-  if ((s = create_fd_sub(p, km, kp, c->stream, &c->sub[1])) != IGAFD_OK) return s;
+  Dir1D merged;
+  if ((s = build_direction(p, p + 1, (int)km.size(), km.data(), &merged)) != IGAFD_OK) return s;
+  if ((s = create_fd_sub(p, patch, merged, c->stream, &c->sub[0])) != IGAFD_OK) return s;
+  if ((s = create_fd_sub(p, merged, patch, c->stream, &c->sub[1])) != IGAFD_OK) return s;
   c->hole = h;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
   *out = c.release();
@@ -1078,6 +1101,10 @@ igafd_status igafd_get_eigen(const igafd_ctx* c, int dir, double* U, double* lam
     return IGAFD_ERR_ARG;
   }
   const Dir1D& d = c->dir[dir];
+  if (d.U.empty()) {
+    set_error("this context holds no univariate eigendecomposition (L-shaped multi-patch context)");
+    return IGAFD_ERR_ARG;
+  }
   if (U) std::memcpy(U, d.U.data(), sizeof(double) * d.U.size());
   if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * d.lam.size());
   return IGAFD_OK;

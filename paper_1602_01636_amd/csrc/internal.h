@@ -50,7 +50,8 @@ struct Dir1D {
   std::vector<double> U, lam;    // n x n row-major (U[i][k] = eigenvector k), n eigenvalues
 };
 
-igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1D* out);
+// eig = false: element tables and M, K only (no eigendecomposition)
+igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1D* out, bool eig = true);
 
 // Device copies of one direction.
 struct DevDir {

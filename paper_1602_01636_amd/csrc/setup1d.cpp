@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -89,32 +91,83 @@ void span_basis(const double* t, int p, int k, double x, double* N, double* dN) 
   }
 }
 
-// Dense Cholesky A = L L^T (lower, row-major, in place).  False if not SPD.
-bool cholesky(std::vector<double>& A, int n) {
+// Runs fn(lo, hi) on contiguous chunks of [0, n) on up to 16 host threads
+// (serially when n < 2 * min_chunk).
+template <class F>
+void parallel_rows(int n, int min_chunk, const F& fn) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int T = (int)std::max(1u, std::min(16u, hw));
+  const int chunks = std::min(T, n / std::max(1, min_chunk));
+  if (chunks <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(chunks);
+  for (int t = 0; t < chunks; ++t)
+    th.emplace_back(fn, (int)((long long)n * t / chunks), (int)((long long)n * (t + 1) / chunks));
+  for (auto& x : th) x.join();
+}
+
+// Largest |i - j| with A_ij != 0 (A n x n, row-major).
+int bandwidth(const std::vector<double>& A, int n) {
+  int bw = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (A[(size_t)i * n + j] != 0.0 || A[(size_t)j * n + i] != 0.0) {
+        bw = std::max(bw, i - j);
+        break;
+      }
+  return bw;
+}
+
+// Cholesky A = L L^T of a band matrix (bandwidth bw; lower factor in place,
+// row-major, upper part zeroed).  The factor keeps the band.  False if not SPD.
+bool cholesky(std::vector<double>& A, int n, int bw) {
   for (int j = 0; j < n; ++j) {
-    double s = A[j * n + j];
-    for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+    double* aj = &A[(size_t)j * n];
+    const int k0 = std::max(0, j - bw);
+    double s = aj[j];
+    for (int k = k0; k < j; ++k) s -= aj[k] * aj[k];
     if (!(s > 0.0)) return false;
     const double ljj = std::sqrt(s);
-    A[j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      double v = A[i * n + j];
-      for (int k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
-      A[i * n + j] = v / ljj;
+    aj[j] = ljj;
+    for (int i = j + 1; i <= std::min(n - 1, j + bw); ++i) {
+      double* ai = &A[(size_t)i * n];
+      double v = ai[j];
+      for (int k = std::max(k0, i - bw); k < j; ++k) v -= ai[k] * aj[k];
+      ai[j] = v / ljj;
     }
-    for (int k = j + 1; k < n; ++k) A[j * n + k] = 0.0;
+    for (int k = j + 1; k < n; ++k) aj[k] = 0.0;
   }
   return true;
+}
+
+// X <- L^-1 X for a band lower factor L (forward substitution on whole rows).
+void forward_rows(const std::vector<double>& L, int n, int bw, std::vector<double>& X) {
+  for (int i = 0; i < n; ++i) {
+    double* xi = &X[(size_t)i * n];
+    for (int k = std::max(0, i - bw); k < i; ++k) {
+      const double l = L[(size_t)i * n + k];
+      const double* xk = &X[(size_t)k * n];
+      for (int j = 0; j < n; ++j) xi[j] -= l * xk[j];
+    }
+    const double d = L[(size_t)i * n + i];
+    for (int j = 0; j < n; ++j) xi[j] /= d;
+  }
 }
 
 // Symmetric eigensolver: Householder reduction to tridiagonal form followed by
 // implicit QR steps with the Wilkinson shift (Golub & Van Loan, Sec. 8.3).
 // S (n x n, row-major) is destroyed; on return lam holds the eigenvalues in
 // ascending order and V the orthonormal eigenvectors as columns (V[i][k]).
+// The QR steps run on the tridiagonal alone; their plane rotations are
+// recorded and applied to V afterwards, a block of rows at a time.
 void symmetric_eig(std::vector<double>& S, int n, std::vector<double>& lam, std::vector<double>& V) {
   V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
   std::vector<double> v(n), pv(n);
+  constexpr int kMinRows = 128;
   // 1. S = Q T Q^T: reflector k zeroes column k below the subdiagonal
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of x = S[k+1:, k]
@@ -132,30 +185,44 @@ void symmetric_eig(std::vector<double>& S, int n, std::vector<double>& lam, std:
     if (nv == 0.0) continue;
     for (int i = 0; i < m; ++i) v[i] /= nv;
     // trailing block B <- H B H = B - 2 v w^T - 2 w v^T, w = B v - (v^T B v) v
-    for (int i = 0; i < m; ++i) {
-      double t = 0.0;
-      for (int j = 0; j < m; ++j) t += S[(size_t)(k + 1 + i) * n + k + 1 + j] * v[j];
-      pv[i] = t;
-    }
+    parallel_rows(m, kMinRows, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        const double* row = &S[(size_t)(k + 1 + i) * n + k + 1];
+        double t = 0.0;
+        for (int j = 0; j < m; ++j) t += row[j] * v[j];
+        pv[i] = t;
+      }
+    });
     double cvp = 0.0;
     for (int i = 0; i < m; ++i) cvp += v[i] * pv[i];
     for (int i = 0; i < m; ++i) pv[i] -= cvp * v[i];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j)
-        S[(size_t)(k + 1 + i) * n + k + 1 + j] -= 2.0 * (v[i] * pv[j] + pv[i] * v[j]);
+    parallel_rows(m, kMinRows, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        double* row = &S[(size_t)(k + 1 + i) * n + k + 1];
+        const double vi = 2.0 * v[i], pi = 2.0 * pv[i];
+        for (int j = 0; j < m; ++j) row[j] -= vi * pv[j] + pi * v[j];
+      }
+    });
     S[(size_t)(k + 1) * n + k] = S[(size_t)k * n + k + 1] = alpha;
     for (int i = 1; i < m; ++i) S[(size_t)(k + 1 + i) * n + k] = S[(size_t)k * n + k + 1 + i] = 0.0;
     // V <- V H on columns k+1..n-1
-    for (int r = 0; r < n; ++r) {
-      double t = 0.0;
-      for (int j = 0; j < m; ++j) t += V[(size_t)r * n + k + 1 + j] * v[j];
-      for (int j = 0; j < m; ++j) V[(size_t)r * n + k + 1 + j] -= 2.0 * t * v[j];
-    }
+    parallel_rows(n, kMinRows, [&](int lo, int hi) {
+      for (int r = lo; r < hi; ++r) {
+        double* row = &V[(size_t)r * n + k + 1];
+        double t = 0.0;
+        for (int j = 0; j < m; ++j) t += row[j] * v[j];
+        t *= 2.0;
+        for (int j = 0; j < m; ++j) row[j] -= t * v[j];
+      }
+    });
   }
   std::vector<double> d(n), e(n, 0.0);
   for (int i = 0; i < n; ++i) d[i] = S[(size_t)i * n + i];
   for (int i = 0; i + 1 < n; ++i) e[i] = S[(size_t)(i + 1) * n + i];
-  // 2. implicit QR steps on unreduced blocks [lo, hi] of the tridiagonal T
+  // 2. implicit QR steps on unreduced blocks [lo, hi] of the tridiagonal T;
+  // rotation j acts on columns (rk[j], rk[j] + 1) of V
+  std::vector<int> rk;
+  std::vector<double> rc, rs;
   const double eps = 2.2e-16;
   int hi = n - 1, guard = 0;
   while (hi > 0 && guard < 100 * n) {
@@ -188,14 +255,35 @@ void symmetric_eig(std::vector<double>& S, int n, std::vector<double>& lam, std:
         z = s * next;        // new bulge at (k, k+2)
         e[k + 1] = c * next;
       }
-      for (int row = 0; row < n; ++row) {
-        double* Vr = &V[(size_t)row * n];
-        const double vk = Vr[k], vk1 = Vr[k + 1];
-        Vr[k] = c * vk + s * vk1;
-        Vr[k + 1] = -s * vk + c * vk1;
-      }
+      rk.push_back(k);
+      rc.push_back(c);
+      rs.push_back(s);
     }
   }
+  // 3. V <- V G_1 G_2 ...: blocks of B rows, stored transposed so that one
+  // rotation updates two contiguous runs of B values
+  constexpr int B = 32;
+  const size_t nrot = rk.size();
+  parallel_rows((n + B - 1) / B, 1, [&](int blo, int bhi) {
+    std::vector<double> T((size_t)n * B);
+    for (int blk = blo; blk < bhi; ++blk) {
+      const int r0 = blk * B, nb = std::min(B, n - r0);
+      for (int j = 0; j < nb; ++j)
+        for (int k = 0; k < n; ++k) T[(size_t)k * B + j] = V[(size_t)(r0 + j) * n + k];
+      for (size_t q = 0; q < nrot; ++q) {
+        double* a = &T[(size_t)rk[q] * B];
+        double* b = a + B;
+        const double c = rc[q], s = rs[q];
+        for (int j = 0; j < B; ++j) {
+          const double va = a[j], vb = b[j];
+          a[j] = c * va + s * vb;
+          b[j] = -s * va + c * vb;
+        }
+      }
+      for (int j = 0; j < nb; ++j)
+        for (int k = 0; k < n; ++k) V[(size_t)(r0 + j) * n + k] = T[(size_t)k * B + j];
+    }
+  });
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
@@ -210,7 +298,7 @@ void symmetric_eig(std::vector<double>& S, int n, std::vector<double>& lam, std:
 
 }  // namespace
 
-igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1D* out) {
+igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1D* out, bool eig) {
   if (p < 1 || p > kMaxDegree) {
     set_error("degree must be in 1.." + std::to_string(kMaxDegree));
     return IGAFD_ERR_ARG;
@@ -301,42 +389,42 @@ igafd_status build_direction(int p, int q, int nknots, const double* knots, Dir1
       }
     }
   }
+  d.U.clear();
+  d.lam.clear();
+  if (!eig) return IGAFD_OK;
   // generalised eigendecomposition K U = M U D, U^T M U = I
+  const int bw = bandwidth(d.M, n);
   std::vector<double> L = d.M;
-  if (!cholesky(L, n)) {
+  if (!cholesky(L, n, bw)) {
     set_error("Cholesky of the 1D mass matrix failed");
     return IGAFD_ERR_NOT_SPD;
   }
-  // X = L^-1 K (forward substitution on each column), then S = X L^-T
+  // S = L^-1 K L^-T = L^-1 (L^-1 K)^T (K symmetric)
   std::vector<double> X = d.K;
-  for (int c = 0; c < n; ++c)
-    for (int i = 0; i < n; ++i) {
-      double v = X[i * n + c];
-      for (int k = 0; k < i; ++k) v -= L[i * n + k] * X[k * n + c];
-      X[i * n + c] = v / L[i * n + i];
-    }
+  forward_rows(L, n, bw, X);
   std::vector<double> S((size_t)n * n);
-  for (int r = 0; r < n; ++r)  // row r of S solves L s = X[r,:]^T  (S = X L^-T)
-    for (int i = 0; i < n; ++i) {
-      double v = X[r * n + i];
-      for (int k = 0; k < i; ++k) v -= L[i * n + k] * S[r * n + k];
-      S[r * n + i] = v / L[i * n + i];
-    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) S[(size_t)j * n + i] = X[(size_t)i * n + j];
+  forward_rows(L, n, bw, S);
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) {
-      const double s = 0.5 * (S[i * n + j] + S[j * n + i]);
-      S[i * n + j] = S[j * n + i] = s;
+      const double s = 0.5 * (S[(size_t)i * n + j] + S[(size_t)j * n + i]);
+      S[(size_t)i * n + j] = S[(size_t)j * n + i] = s;
     }
   std::vector<double> Ut;
   symmetric_eig(S, n, d.lam, Ut);
-  // U = L^-T Ut: back substitution with L^T on each column
-  d.U.assign((size_t)n * n, 0.0);
-  for (int c = 0; c < n; ++c)
-    for (int i = n - 1; i >= 0; --i) {
-      double v = Ut[i * n + c];
-      for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * d.U[k * n + c];
-      d.U[i * n + c] = v / L[i * n + i];
+  // U = L^-T Ut: backward substitution on whole rows, L^T upper with band bw
+  d.U = Ut;
+  for (int i = n - 1; i >= 0; --i) {
+    double* ui = &d.U[(size_t)i * n];
+    for (int k = i + 1; k <= std::min(n - 1, i + bw); ++k) {
+      const double l = L[(size_t)k * n + i];
+      const double* uk = &d.U[(size_t)k * n];
+      for (int j = 0; j < n; ++j) ui[j] -= l * uk[j];
     }
+    const double dd = L[(size_t)i * n + i];
+    for (int j = 0; j < n; ++j) ui[j] /= dd;
+  }
   return IGAFD_OK;
 }
 

@@ -7,7 +7,10 @@ what it can compute one by one or whole:
 * sampled rows of A x and of b (the oracle assembles only the elements that
   touch those rows): 1e-12 relative to sum_j |a_ij x_j| per row;
 * the whole FD apply P^-1 r (the oracle's mode products are cheap): FP64
-  1e-11, FP32 1e-4, BF16 5e-2 relative (as in the small-size tests);
+  1e-11, FP32 1e-4, BF16 5e-2 relative (as in the small-size tests); for
+  the L-shaped domain, whose two-patch direction has n = 2051 and a 1D
+  condition number kappa ~ 2e7, FP64 max(1e-11, eps kappa) (the small
+  eigenvalues of a 1D pencil are determined only to relative eps kappa);
 * the Prop. 1 spectral bounds against their closed form on the ring;
 * the solve: the library's FP64 true residual <= 1e-8, and on the sampled
   rows the oracle's own residual b_i - (A u)_i of the library's u is within
@@ -16,7 +19,8 @@ what it can compute one by one or whole:
 Workloads: thick quarter ring p=3 128^3; warped cube with kappa p=5 96^3
 (BF16 FD, flexible CG); warped cube p=4 112^3 with the diagonal-ratio scaling;
 2D square p=3 64^2 (whole oracle solve); the 64-problem batch (sampled rows
-of three of its problems).
+of three of its problems); the L-shaped three-patch domain, h^-1 = 1024 per
+patch, p = 3, with the additive Schwarz preconditioner.
 """
 import numpy as np
 import pytest
@@ -184,3 +188,71 @@ def test_batch_64_sampled(api):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_lshape_1024_p3(api):
+    """L-shaped three-patch domain at h^-1 = 1024 per patch, p = 3 (3.15 M
+    unknowns): sampled rows of A x (interfaces, the re-entrant corner, the
+    outer boundary, seeded interior rows) from the oracle's glued patch sums;
+    the whole P_IAS apply and load vector; the solve's residual on the
+    sampled rows."""
+    from oracle import multipatch as mp
+    p, E = 3, 1024
+    knots = synth.uniform_knots(E, p)
+    L = mp.LShape(knots, p)
+    pos, n = L.square_index()
+    gid_of = np.full(n * n, -1, dtype=np.int64)
+    gid_of[pos] = np.arange(L.N)
+    h = L.m - 2
+    picks = set()
+    for i1, i2 in [(0, 0), (h - 1, h), (h, h - 1), (h - 1, h - 1), (h, 0), (0, h), (n - 1, 0), (0, n - 1),
+                   (n - 1, h - 1), (h - 1, n - 1), (h - 2, h + 3), (h + 3, h - 2), (h // 2, h), (h, h // 2)]:
+        picks.add(i2 * n + i1)
+    rng = np.random.default_rng(41)
+    while len(picks) < 64:
+        q = int(rng.choice(pos))
+        picks.add(q)
+    sq = np.array(sorted(picks))
+    assert np.all(gid_of[sq] >= 0)
+    A_r = L.matrix_rows(gid_of[sq])
+    with api.igafd_lshape_setup(knots, p) as ctx:
+        assert ctx.n[0] == n and ctx.ndofs == L.N
+        x = np.random.default_rng(42).standard_normal(n * n)
+        y = to_dev(np.zeros(n * n))
+        api.igafd_apply_A(ctx, to_dev(x), y)
+        yg = to_host(y)
+        ref = A_r @ x[pos]
+        scale = abs(A_r) @ np.abs(x[pos])
+        assert np.max(np.abs(yg[sq] - ref) / scale) < 1e-12
+        out = np.ones(n * n, dtype=bool)
+        out[pos] = False
+        assert np.all(yg[out] == 0.0)
+        # P_IAS^-1 r, whole vector
+        S = mp.Schwarz(L)
+        r = np.random.default_rng(43).standard_normal(n * n)
+        ref = S.ias(r[pos])
+        # FP64 bound: the small eigenvalues of a 1D pencil (K, M) are fixed by any
+        # backward-stable eigensolver only to eps * lam_max, i.e. relatively to
+        # eps * kappa, kappa = lam_max / lam_min (2e7 for the two-patch direction
+        # at this size); P^-1 weights those modes most, so the two independent
+        # eigendecompositions (library, oracle) agree to about eps * kappa
+        kappa = max(F[d]["lam"].max() / F[d]["lam"].min() for F in S.factors for d in range(2))
+        for prec, tol in (("fp64", max(1e-11, 2.2e-16 * kappa / 2)), ("fp32", 1e-4), ("bf16", 5e-2)):
+            s = to_dev(np.zeros(n * n))
+            api.igafd_apply_precond(ctx, prec, to_dev(r), s)
+            sg = to_host(s)
+            assert rel(sg[pos], ref) < tol, prec
+            assert np.all(sg[out] == 0.0)
+        # load vector and the solve
+        b = to_dev(np.zeros(n * n))
+        api.igafd_load_vector(ctx, synth.RHS_PAPER_POLY, b)
+        bg = to_host(b)
+        b_or = L.load(synth.RHS_PAPER_POLY)
+        assert rel(bg[pos], b_or) < 1e-13
+        u = to_dev(np.zeros(n * n))
+        info = api.igafd_solve(ctx, b, u, rtol=1e-8)
+        assert info["status"] == "OK" and info["true_relres"] <= 1e-8 and info["iters"] <= 30
+        ug = to_host(u)
+        res = b_or[gid_of[sq]] - A_r @ ug[pos]
+        slack = 1e-11 * (abs(A_r) @ np.abs(ug[pos]))
+        assert np.all(np.abs(res) <= 1e-8 * np.linalg.norm(b_or) + slack)

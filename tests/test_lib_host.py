@@ -40,6 +40,23 @@ def test_univariate_matches_oracle(p):
     np.testing.assert_allclose(U.T @ Ko @ U, np.diag(lo), atol=1e-9 * lo.max())
 
 
+@pytest.mark.parametrize("p", [2, 5])
+def test_univariate_large_threaded(p):
+    # several row blocks and threads in the host eigensolver; a p-fold
+    # interior knot (the two-patch knot vector of the L-shaped domain) gives
+    # nearly equal eigenvalue pairs
+    from oracle import multipatch as mp
+    from paper_1602_01636_amd import igafd_univariate
+    kn = mp.merged_knots(synth.jittered_knots(200, p, seed=p), p)
+    M, K, U, lam = igafd_univariate(p, kn)
+    Mo, Ko = splines.univariate_matrices(kn, p)
+    _, lo = fd.generalized_eig(Ko, Mo)
+    assert len(lam) > 400
+    np.testing.assert_allclose(lam, lo, rtol=1e-10)
+    np.testing.assert_allclose(U.T @ Mo @ U, np.eye(len(lam)), atol=1e-10)
+    np.testing.assert_allclose(U.T @ Ko @ U, np.diag(lo), atol=1e-9 * lo.max())
+
+
 def test_univariate_repeated_knots_and_errors():
     from paper_1602_01636_amd import IgafdError, igafd_univariate
     kn = np.array([0, 0, 0, 0, 0.25, 0.5, 0.5, 0.75, 1, 1, 1, 1], float)
