@@ -260,6 +260,7 @@ igafd_status create_fd_sub(int p, const Dir1D& d1, const Dir1D& d2, hipStream_t 
   c->N = 1;
   c->dir[0] = d1;
   c->dir[1] = d2;
+  if (const char* e = std::getenv("IGAFD_FD_GEMM")) c->fd_gemm = std::atoi(e) != 0;
   igafd_status s;
   for (int l = 0; l < 2; ++l) {
     c->n[l] = c->dir[l].n;
@@ -407,13 +408,13 @@ igafd_status read_state(igafd_ctx* c) {
 // z = M r with M = P^-1 or S P^-1 S; (r, z) partials; then rho or beta.
 igafd_status precond_step(igafd_ctx* c, int prec, const double* S, double* z, int which, const int* flag) {
   IGAFD_TRY(fd_apply(c, prec, c->r, z, S, c->partial, flag));
-  return reduce(c, fd_dot_blocks(c), 0, which, nullptr);
+  return reduce(c, fd_dot_blocks(c, prec), 0, which, nullptr);
 }
 
 // (Re)start: r holds the residual; z = M r, rho = (r, z), p = z.
 igafd_status start_directions(igafd_ctx* c, int prec, const double* S, double*& z, double*& zold) {
   IGAFD_TRY(fd_apply(c, prec, c->r, z, S, c->partial, nullptr));
-  IGAFD_TRY(reduce(c, fd_dot_blocks(c), 0, RED_RHO0, nullptr));
+  IGAFD_TRY(reduce(c, fd_dot_blocks(c, prec), 0, RED_RHO0, nullptr));
   hipLaunchKernelGGL(k_update_p, dim3(vblocks(c)), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 1, c->N);
   IGAFD_HIP_CHECK(hipGetLastError());
   (void)zold;
@@ -873,6 +874,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
   if (const char* e = std::getenv("IGAFD_FD_TILES")) c->fd_tiles = std::atoi(e);
   if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
   if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IGAFD_FD_GEMM")) c->fd_gemm = std::atoi(e) != 0;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
   if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
   {

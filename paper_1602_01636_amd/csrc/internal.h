@@ -102,6 +102,7 @@ struct igafd_ctx {
   long long ext_cap = 0;                   // doubles allocated at ext
   int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
   int fd_fused = 1;                        // 3D: three fused passes instead of six products
+  int fd_gemm = -1;                        // 2D: tiled products (1), per-strip products (0), by size (-1)
   // L-shaped multi-patch context: the grid is the bounding square's, the
   // quarter i1 >= hole && i2 >= hole is not part of the domain (held at zero);
   // sub[0], sub[1]: preconditioner-only contexts of the two Schwarz subdomains
@@ -142,7 +143,7 @@ igafd_status mask_hole(igafd_ctx* c, double* y);
 // fd.hip
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                       double* partial_rz, const int* flag);
-int fd_dot_blocks(const igafd_ctx* c);
+int fd_dot_blocks(const igafd_ctx* c, int prec);
 int fd_dot_blocks_max(const igafd_ctx* c);
 int fd_npad(int n);
 bool fd_fused_ok(const igafd_ctx* c);

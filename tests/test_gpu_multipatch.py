@@ -167,3 +167,28 @@ def test_lshape_rejects_single_patch_only_calls(api):
         # a single-patch context reports no removed quarter
         with api.igafd_setup(synth.square_2d(E=6, p=2)) as c2:
             assert api.igafd_lshape_corner(c2) == (-1, c2.N)
+
+
+@pytest.mark.parametrize("name,knots,p", CASES, ids=IDS)
+def test_lshape_tiled_products(api, name, knots, p, monkeypatch):
+    """The subdomain applies by tiled products (forced on: every tile ragged)."""
+    monkeypatch.setenv("IGAFD_FD_GEMM", "1")
+    ctx, L, S, pos, n = setup_case(api, name, knots, p)
+    with ctx:
+        r = synth.random_vector(n * n, 34)
+        ref = S.ias(r[pos])
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2)):
+            s = to_dev(np.full(n * n, 5.0))
+            api.igafd_apply_precond(ctx, prec, to_dev(r), s)
+            sg = to_host(s)
+            assert rel(sg[pos], ref) < tol, prec
+            assert np.all(sg[outside(pos, n)] == 0.0), prec
+        if name != "single_interior_p2":
+            b = L.load(synth.RHS_PAPER_POLY)
+            u_or, info_or = S.solve(b, "ias")
+            bs = np.zeros(n * n)
+            bs[pos] = b
+            u = to_dev(np.zeros(n * n))
+            info = api.igafd_solve(ctx, to_dev(bs), u, rtol=1e-8)
+            assert info["true_relres"] <= 1e-8 and abs(info["iters"] - info_or["iters"]) <= 1
+            assert rel(to_host(u)[pos], u_or) <= 1e-7

@@ -286,3 +286,49 @@ def test_edge_cases(api):
         api.igafd_setup(synth.uniform_problem(3, 3, 1, geometry=g))
     with pytest.raises(IgafdError):
         api.igafd_setup(synth.make_problem(3, 2, [synth.uniform_knots(3, 2)] * 3, quad=5))
+
+
+GEMM_2D = [
+    ("2d_ragged_p3", synth.uniform_problem(2, [37, 70], 3, geometry=synth.warped_geometry(4, dim=2),
+                                           coefficient=synth.sincos_coefficient(0.3, 1, 2, 0.1, 0.2))),
+    ("2d_jittered_p5", synth.make_problem(2, 5, [synth.jittered_knots(150, 5, 3), synth.jittered_knots(21, 5, 4)])),
+    ("2d_annulus_p1", synth.uniform_problem(2, [130, 129], 1, geometry={"kind": "ring"})),
+]
+
+
+@pytest.mark.parametrize("name,prob", GEMM_2D, ids=[g[0] for g in GEMM_2D])
+def test_2d_tiled_products(api, name, prob, rng, monkeypatch):
+    """The 2D apply by tiled products (forced on at sizes whose tiles are all
+    ragged): applies against the oracle, plain and scaled, and the solve
+    (whose (r, s) partials come from the last product's epilogue) against
+    the per-strip products."""
+    A = assembly.assemble_matrix(prob)
+    F = fd.setup(prob)
+    monkeypatch.setenv("IGAFD_FD_GEMM", "1")
+    with api.igafd_setup(prob) as ctx:
+        r = rng.standard_normal(ctx.N)
+        ref = fd.fd_apply(F, r)
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2)):
+            s = to_dev(np.full(ctx.N, 3.0))
+            api.igafd_apply_precond(ctx, prec, to_dev(r), s)
+            assert rel(to_host(s), ref) < tol, prec
+        S = np.exp(0.1 * rng.standard_normal(ctx.N))
+        api.igafd_set_scaling(ctx, to_dev(S))
+        s = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_precond(ctx, "fp64", to_dev(r), s)
+        assert rel(to_host(s), S * fd.fd_apply(F, S * r)) < 1e-11
+        u = to_dev(np.zeros(ctx.N))
+        info_s = api.igafd_solve(ctx, to_dev(A @ r), u, use_scaling=True)
+        assert info_s["true_relres"] <= 1e-8
+        api.igafd_set_scaling(ctx, None)
+        b = A @ rng.standard_normal(ctx.N)
+        u = to_dev(np.zeros(ctx.N))
+        info = api.igafd_solve(ctx, to_dev(b), u)
+        u32 = to_dev(np.zeros(ctx.N))
+        info32 = api.igafd_solve(ctx, to_dev(b), u32, precision="fp32")
+    assert info["true_relres"] <= 1e-8 and info32["true_relres"] <= 1e-8
+    monkeypatch.setenv("IGAFD_FD_GEMM", "0")
+    with api.igafd_setup(prob) as ctx0:
+        u0 = to_dev(np.zeros(ctx0.N))
+        info0 = api.igafd_solve(ctx0, to_dev(b), u0)
+    assert info["iters"] == info0["iters"] and rel(to_host(u), to_host(u0)) < 1e-10
