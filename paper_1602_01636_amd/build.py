@@ -1,6 +1,7 @@
 """Build the HIP library libigafd.so in-tree for gfx950 (hipcc)."""
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -26,17 +27,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# extra flags per source file
+PER_FILE_FLAGS = {
+    # MFMA accumulators in VGPRs: in AGPRs the compiler copied every accumulator
+    # between the register files on each K slice of the tiled products
+    "gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, "-c", *PER_FILE_FLAGS.get(os.path.basename(src), []), *inc, src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    workers = max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+        results = list(pool.map(compile_one, srcs))
+    objs = []
+    for src, (obj, res) in zip(srcs, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)}")
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *srcs, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError("hipcc link failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -244,230 +244,6 @@ igafd_status launch_mode(hipStream_t st, int mt_max, const Tin* X, Tout* Y, cons
 }
 
 // ------------------------------------------------------------------------
-// Mode products of long directions (2D grids with n_d in the hundreds or
-// thousands) as tiled dense products
-//   C (M x N) = A (M x K) B,   B = Bm (K x N)  or  Bm^T (Bm stored N x K),
-// all row-major.  A block computes a BM x BN tile of C from BK-deep slices of
-// A and B staged in LDS k-major (double-buffered: the next slice's global
-// loads are in flight while the current one feeds the MFMAs); four waves in a
-// 2 x 2 grid, each TM x TN tiles of 16 x 16.  Epilogue: optional division by
-// lrow[m] + lcol[n] (the eigenvalue sums of the FD scaling), optional
-// diagonal scalings of the input (A) and output, optional (r, C) block
-// partials.  Tiles go to the 8 XCDs in contiguous runs (blockIdx % 8 is the
-// XCD), so blocks that share an A row panel share an L2.
-// ------------------------------------------------------------------------
-template <class Pr>
-struct GemmV;
-template <>
-struct GemmV<PF64> {
-  using V = double;
-};
-template <>
-struct GemmV<PF32> {
-  using V = float;
-};
-
-__device__ inline d4_t gemm_mma(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ inline f4_t gemm_mma(float a, float b, f4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-constexpr int kGemmBK = 16;
-
-struct GEpi {
-  const double* lrow = nullptr;  // with lcol: C[m][n] /= lrow[m] + lcol[n]
-  const double* lcol = nullptr;
-  const double* Sa = nullptr;    // A[m][k] *= Sa[m * lda + k] on load
-  const double* Sc = nullptr;    // C[m][n] *= Sc[m * ldc + n]
-  const double* rdot = nullptr;  // with partial: block sums of rdot[m * ldc + n] * C[m][n]
-  double* partial = nullptr;
-  const int* flag = nullptr;     // CG stop flag: nonzero -> the launch is a no-op
-};
-
-template <int TM, int TN, typename V>
-constexpr size_t gemm_lds_bytes() {
-  return sizeof(V) * 2 * kGemmBK * ((2 * TM * 16 + 4) + (2 * TN * 16 + 4));
-}
-
-template <class Pr, int TM, int TN, bool BT, typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(kBlock) void k_gemm(const TA* __restrict__ A, long long lda, const TB* __restrict__ B,
-                                                 long long ldb, TC* __restrict__ C, long long ldc, int M, int N,
-                                                 int K, int tiles_n, int ntiles, GEpi ep) {
-  using V = typename GemmV<Pr>::V;
-  using acc_t = typename Pr::acc;
-  constexpr int BM = 2 * TM * 16, BN = 2 * TN * 16, BK = kGemmBK;
-  constexpr int LA = BM + 4, LB = BN + 4;  // padded k-rows of the LDS slices
-  constexpr int EA = BM * BK / kBlock, EB = BN * BK / kBlock;
-  constexpr int APR = BK / EA;                       // threads per row of the A slice
-  constexpr int BPR = BT ? BK / EB : BN / EB;        // threads per row of the stored B slice
-  extern __shared__ __align__(16) unsigned char gsm[];
-  V* As = reinterpret_cast<V*>(gsm);  // [2][BK][LA]
-  V* Bs = As + 2 * BK * LA;           // [2][BK][LB]
-  if (ep.flag && *ep.flag) return;
-  const int per = (ntiles + 7) / 8;
-  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (tile >= ntiles) {
-    if (ep.partial && threadIdx.x == 0) ep.partial[blockIdx.x] = 0.0;
-    return;
-  }
-  const int tm0 = (tile / tiles_n) * BM, tn0 = (tile % tiles_n) * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int col = lane & 15, grp = lane >> 4;
-  const int wm0 = (wave >> 1) * TM * 16, wn0 = (wave & 1) * TN * 16;
-  const int ar = tid / APR, ak = (tid % APR) * EA;
-  const int br = tid / BPR, bc = (tid % BPR) * EB;
-
-  V ra[EA], rb[EB];
-  auto load = [&](int k0) {
-    const int m = tm0 + ar;
-#pragma unroll
-    for (int j = 0; j < EA; ++j) {
-      const int k = k0 + ak + j;
-      double v = 0.0;
-      if (m < M && k < K) {
-        const long long a = (long long)m * lda + k;
-        v = (double)A[a];
-        if (ep.Sa) v *= ep.Sa[a];
-      }
-      ra[j] = (V)v;
-    }
-#pragma unroll
-    for (int j = 0; j < EB; ++j) {
-      // BT: Bm row br = n, columns bc + j = k;  else Bm row br = k, columns bc + j = n
-      const int n = BT ? tn0 + br : tn0 + bc + j;
-      const int k = BT ? k0 + bc + j : k0 + br;
-      rb[j] = (n < N && k < K) ? (V)B[BT ? (long long)n * ldb + k : (long long)k * ldb + n] : V(0);
-    }
-  };
-  auto store = [&](int buf) {
-    V* as = As + buf * BK * LA;
-    V* bs = Bs + buf * BK * LB;
-#pragma unroll
-    for (int j = 0; j < EA; ++j) as[(ak + j) * LA + ar] = ra[j];
-#pragma unroll
-    for (int j = 0; j < EB; ++j) {
-      if (BT)
-        bs[(bc + j) * LB + br] = rb[j];
-      else
-        bs[br * LB + bc + j] = rb[j];
-    }
-  };
-
-  acc_t acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
-    const V* as = As + buf * BK * LA;
-    const V* bs = Bs + buf * BK * LB;
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      V a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = as[(ks + grp) * LA + wm0 + i * 16 + col];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = bs[(ks + grp) * LB + wn0 + j * 16 + col];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = gemm_mma(a[i], b[j], acc[i][j]);
-    }
-    if (kt + 1 < nk) store(buf ^ 1);
-    __syncthreads();
-  }
-
-  double dot = 0.0;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = tm0 + wm0 + i * 16 + (Pr::ROW_STRIDE4 ? grp + 4 * r : 4 * grp + r);
-        const int n = tn0 + wn0 + j * 16 + col;
-        if (m < M && n < N) {
-          double v = (double)acc[i][j][r];
-          const long long c = (long long)m * ldc + n;
-          if (ep.lrow) v /= ep.lrow[m] + ep.lcol[n];
-          if (ep.Sc) v *= ep.Sc[c];
-          C[c] = (TC)v;
-          if (ep.partial) dot += ep.rdot[c] * v;
-        }
-      }
-  if (ep.partial) {
-    const double sum = block_sum(dot);
-    if (threadIdx.x == 0) ep.partial[blockIdx.x] = sum;
-  }
-}
-
-struct GemmCfg {
-  int tm, tn;
-};
-
-int device_cus() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
-  return cus;
-}
-
-// The largest tile (fewer re-reads of A and B) that still gives two blocks
-// per CU, within 64 KB of LDS; else the smallest.
-// (The choice does not depend on the precision, so the number of blocks of the
-// last pass, which carry the (r, s) partials, is known from the shape alone.)
-GemmCfg gemm_cfg(int M, int N) {
-  const GemmCfg cand[4] = {{4, 4}, {4, 2}, {2, 4}, {2, 2}};
-  const long long want = 2LL * device_cus();
-  for (const GemmCfg& g : cand) {
-    const size_t lds = sizeof(double) * 2 * kGemmBK * ((2 * g.tm * 16 + 4) + (2 * g.tn * 16 + 4));
-    if (lds > 64 * 1024) continue;
-    const long long tiles = (long long)((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
-    if (tiles >= want) return g;
-  }
-  return {2, 2};
-}
-
-int gemm_grid(int M, int N, GemmCfg g) {
-  const int tiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
-  return 8 * ((tiles + 7) / 8);
-}
-
-template <class Pr, bool BT, typename TA, typename TB, typename TC>
-igafd_status launch_gemm(hipStream_t st, const TA* A, long long lda, const TB* B, long long ldb, TC* C, long long ldc,
-                         int M, int N, int K, const GEpi& ep) {
-  using V = typename GemmV<Pr>::V;
-  const GemmCfg g = gemm_cfg(M, N);
-  const int tiles_n = (N + 32 * g.tn - 1) / (32 * g.tn);
-  const int ntiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * tiles_n;
-  const dim3 grid((unsigned)gemm_grid(M, N, g));
-#define IGAFD_G(TM, TN)                                                                                          \
-  if (g.tm == TM && g.tn == TN) {                                                                                \
-    constexpr size_t lds = gemm_lds_bytes<TM, TN, V>();                                                          \
-    hipLaunchKernelGGL((k_gemm<Pr, TM, TN, BT, TA, TB, TC>), grid, dim3(kBlock), lds, st, A, lda, B, ldb, C, ldc, \
-                       M, N, K, tiles_n, ntiles, ep);                                                           \
-    IGAFD_HIP_CHECK(hipGetLastError());                                                                          \
-    return IGAFD_OK;                                                                                             \
-  }
-  IGAFD_G(4, 4) IGAFD_G(4, 2) IGAFD_G(2, 4) IGAFD_G(2, 2)
-#undef IGAFD_G
-  set_error("internal: bad GEMM tile");
-  return IGAFD_ERR_ARG;
-}
-
-// ------------------------------------------------------------------------
 // Fused 3D passes.  The mode products of different directions commute, so
 // the apply is done in three passes over the tensor instead of six:
 //   A  per i3 slice X (n2 x n1):  Y = V2 (X V1^T)       directions 1, 2 forward
@@ -918,55 +694,13 @@ int dot_blocks_for(const igafd_ctx* c) {
   return grid_x(C, 1, ms.nblk);
 }
 
-// 2D applies of long directions use the tiled products (FP64 and FP32;
-// IGAFD_FD_GEMM=0/1 at setup forces the choice)
+// 2D applies of long directions use the tiled products of gemm.hip (FP64 and
+// FP32; IGAFD_FD_GEMM=0/1 at setup forces the choice)
 constexpr int kGemmAutoN = 384;
 bool use_gemm(const igafd_ctx* c, int prec) {
   if (c->dim != 2 || prec == IGAFD_BF16) return false;
   if (c->fd_gemm >= 0) return c->fd_gemm != 0;
   return c->n[0] + c->n[1] >= kGemmAutoN;
-}
-
-// 2D apply by four tiled products on the row-major (n2 x n1) grid:
-//   T = R U1 (forward, direction 1), Y = (U2^T T) / (lam2 + lam1),
-//   Z = U2 Y, S = Z U1^T; r and s may be sub-blocks of wider grids (ldr, lds).
-template <class Pr, typename T>
-igafd_status apply_gemm2d(igafd_ctx* c, const double* r, double* s, const double* S, double* partial,
-                          const int* flag, int ldr, int lds) {
-  using V = typename GemmV<Pr>::V;
-  const DevDir* d = c->ddir;
-  const int n1 = c->n[0], n2 = c->n[1];
-  if (ldr <= 0) ldr = n1;
-  if (lds <= 0) lds = n1;
-  T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
-  T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
-  const V* W1f = wmat<Pr>(d[0], 0);
-  const V* W1b = wmat<Pr>(d[0], 1);
-  const V* W2f = wmat<Pr>(d[1], 0);
-  const V* W2b = wmat<Pr>(d[1], 1);
-  const hipStream_t st = c->stream;
-  GEpi e1, e2, e3, e4;
-  e1.flag = e2.flag = e3.flag = e4.flag = flag;
-  e1.Sa = S;
-  e2.lrow = d[1].lam;
-  e2.lcol = d[0].lam;
-  e4.Sc = S;
-  if (partial) {
-    if (gemm_grid(n2, n1, gemm_cfg(n2, n1)) > c->npartial) {
-      set_error("internal: FD grid larger than the partial-sum buffer");
-      return IGAFD_ERR_ARG;
-    }
-    e4.rdot = r;
-    e4.partial = partial;
-  }
-  igafd_status stt;
-  if ((stt = launch_gemm<Pr, true, double, V, T>(st, r, ldr, W1f, d[0].npad, b0, n1, n2, n1, n1, e1)) != IGAFD_OK)
-    return stt;
-  if ((stt = launch_gemm<Pr, false, V, T, T>(st, W2f, d[1].npad, b0, n1, b1, n1, n2, n1, n2, e2)) != IGAFD_OK)
-    return stt;
-  if ((stt = launch_gemm<Pr, false, V, T, T>(st, W2b, d[1].npad, b1, n1, b0, n1, n2, n1, n2, e3)) != IGAFD_OK)
-    return stt;
-  return launch_gemm<Pr, true, T, V, double>(st, b0, n1, W1b, d[0].npad, s, lds, n2, n1, n1, e4);
 }
 
 // T: intermediate type (double for FP64, float otherwise)
@@ -1020,9 +754,10 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
                                              (long long)n1 * n2, e0)));
     IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
   } else {
-    if constexpr (!std::is_same<Pr, PBF16>::value)
-      if (use_gemm(c, std::is_same<Pr, PF64>::value ? IGAFD_FP64 : IGAFD_FP32))
-        return apply_gemm2d<Pr, T>(c, r, s, S, partial, flag, ldr, lds);
+    if constexpr (!std::is_same<Pr, PBF16>::value) {
+      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : IGAFD_FP32;
+      if (use_gemm(c, prec)) return fd_apply_gemm2d(c, prec, r, s, S, partial, flag, ldr, lds);
+    }
     IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in,
                                                  ldr, n1)));
     e_lam.lamK = d[1].lam;
@@ -1119,14 +854,14 @@ bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c); }
 
 int fd_dot_blocks(const igafd_ctx* c, int prec) {
   if (c->hole >= 0) return schwarz_blocks(c);
-  if (use_gemm(c, prec)) return gemm_grid(c->n[1], c->n[0], gemm_cfg(c->n[1], c->n[0]));
+  if (use_gemm(c, prec)) return fd_gemm_blocks(c);
   return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c);
 }
 
 int fd_dot_blocks_max(const igafd_ctx* c) {
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
   int m = std::max(slice_blocks(c), schwarz_blocks(c));
-  if (c->dim == 2) m = std::max(m, gemm_grid(c->n[1], c->n[0], gemm_cfg(c->n[1], c->n[0])));
+  if (c->dim == 2) m = std::max(m, fd_gemm_blocks(c));
   for (int t = 1; t <= 8; ++t) {
     const int g = grid_x(C, 1, mode_shape(c->n[0], t).nblk);
     if (g > m) m = g;

@@ -1,0 +1,397 @@
+// Mode products of long directions (2D grids with n_d in the hundreds or
+// thousands) as tiled dense products on the MFMA units.
+//
+// The 2D fast-diagonalisation apply (Sec. 4.1, Alg. 1) on a row-major
+// (n2 x n1) grid is four products
+//   T = R U1,  Y = (U2^T T) / (lam2 (+) lam1),  Z = U2 Y,  S = Z U1^T,
+// each of the form C (M x N) = A (M x K) B with B = Bm (K x N) or Bm^T
+// (Bm stored N x K), all row-major.  A block computes a BM x BN tile of C
+// from BK-deep slices of A and B staged in LDS k-major (double-buffered);
+// four waves in a 2 x 2 grid, each TM x TN tiles of 16 x 16
+// (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4).  Global loads run two slices
+// ahead: slice t+2 is loading while slice t feeds the MFMAs and slice t+1
+// goes from registers to LDS; loads use clamped (in-bounds) indices and the
+// values outside the matrices are zeroed only when they are stored to LDS,
+// so no load is waited for early.  Epilogue: division by lam_row[m] +
+// lam_col[n], the diagonal scalings of S P^-1 S, (r, s) block partials.
+// Tiles go to the 8 XCDs in contiguous runs (blockIdx % 8 is the XCD), so
+// blocks that share an A row panel share an L2.
+//
+// This file is compiled with the MFMA accumulators in VGPRs (the build's
+// per-file flags): with them in AGPRs the compiler copied all accumulators
+// between the register files on every slice.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace igafd {
+namespace {
+
+typedef double gd4_t __attribute__((ext_vector_type(4)));
+typedef float gf4_t __attribute__((ext_vector_type(4)));
+typedef double gd2u_t __attribute__((ext_vector_type(2), aligned(8)));
+typedef float gf4u_t __attribute__((ext_vector_type(4), aligned(4)));
+
+// Operand layouts (gfx950): A lane l holds row l%16, B lane l holds column
+// l%16, both with contracted index l/16.  Result register r of lane l holds
+// column l%16 and row l/16 + 4r (f64) or 4(l/16) + r (f32).
+struct G64 {
+  using V = double;
+  using acc = gd4_t;
+  static constexpr bool ROW_STRIDE4 = true;
+};
+struct G32 {
+  using V = float;
+  using acc = gf4_t;
+  static constexpr bool ROW_STRIDE4 = false;
+};
+
+__device__ inline gd4_t mma(double a, double b, gd4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline gf4_t mma(float a, float b, gf4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kBK = 16;
+// LDS row padding (elements): the four lane groups of an MFMA operand read
+// four consecutive k-rows; a 16-element shift puts each group on its own banks
+constexpr int kPad = 16;
+
+struct GEpi {
+  const double* lrow = nullptr;  // with lcol: C[m][n] /= lrow[m] + lcol[n]
+  const double* lcol = nullptr;
+  const double* Sa = nullptr;    // A[m][k] *= Sa[m * lda + k] (PRE)
+  const double* Sc = nullptr;    // C[m][n] *= Sc[m * ldc + n]
+  const double* rdot = nullptr;  // with partial: block sums of rdot[m * ldc + n] * C[m][n]
+  double* partial = nullptr;
+  const int* flag = nullptr;     // CG stop flag: nonzero -> the launch is a no-op
+};
+
+template <int TM, int TN, typename V>
+constexpr size_t lds_bytes() {
+  return sizeof(V) * 2 * kBK * ((2 * TM * 16 + kPad) + (2 * TN * 16 + kPad));
+}
+
+// N consecutive values from p (8- or 4-byte aligned), as V
+template <int N, typename T, typename V>
+__device__ inline void ldv(const T* p, V* o) {
+  if constexpr (sizeof(T) == 8) {
+    static_assert(N % 2 == 0, "pairs of doubles");
+#pragma unroll
+    for (int j = 0; j < N; j += 2) {
+      const gd2u_t u = *reinterpret_cast<const gd2u_t*>(p + j);
+      o[j] = (V)u.x;
+      o[j + 1] = (V)u.y;
+    }
+  } else {
+    static_assert(N % 4 == 0, "quads of floats");
+#pragma unroll
+    for (int j = 0; j < N; j += 4) {
+      const gf4u_t u = *reinterpret_cast<const gf4u_t*>(p + j);
+      o[j] = (V)u.x;
+      o[j + 1] = (V)u.y;
+      o[j + 2] = (V)u.z;
+      o[j + 3] = (V)u.w;
+    }
+  }
+}
+
+// PRE: A is scaled by ep.Sa (the input scaling of S P^-1 S)
+template <class G, int TM, int TN, bool BT, bool PRE, typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(kBlock) void k_gemm(const TA* __restrict__ A, long long lda, const TB* __restrict__ B,
+                                                 long long ldb, TC* __restrict__ C, long long ldc, int M, int N,
+                                                 int K, int tiles_n, int ntiles, GEpi ep) {
+  using V = typename G::V;
+  using acc_t = typename G::acc;
+  constexpr int BM = 2 * TM * 16, BN = 2 * TN * 16, BK = kBK;
+  constexpr int LA = BM + kPad, LB = BN + kPad;
+  constexpr int EA = BM * BK / kBlock, EB = BN * BK / kBlock;  // values per thread per slice
+  constexpr int APR = BK / EA;                                 // threads per row of the A slice
+  constexpr int BPR = BT ? BK / EB : BN / EB;                  // threads per row of the stored B slice
+  extern __shared__ __align__(16) unsigned char gsm[];
+  V* As = reinterpret_cast<V*>(gsm);  // [2][BK][LA]
+  V* Bs = As + 2 * BK * LA;           // [2][BK][LB]
+  if (ep.flag && *ep.flag) return;
+  const int per = (ntiles + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntiles) {
+    if (ep.partial && threadIdx.x == 0) ep.partial[blockIdx.x] = 0.0;
+    return;
+  }
+  const int tm0 = (tile / tiles_n) * BM, tn0 = (tile % tiles_n) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int wm0 = (wave >> 1) * TM * 16, wn0 = (wave & 1) * TN * 16;
+  const int ar = tid / APR, ak = (tid % APR) * EA;
+  const int br = tid / BPR, bc = (tid % BPR) * EB;
+  // this thread's A row and (BT) Bm row, clamped into the matrices
+  const int am = tm0 + ar;
+  const bool am_ok = am < M;
+  const TA* arow = A + (long long)(am_ok ? am : M - 1) * lda;
+  const double* srow = PRE ? ep.Sa + (long long)(am_ok ? am : M - 1) * lda : nullptr;
+  const int bn = BT ? tn0 + br : tn0 + bc;  // BT: row of Bm; else first column
+  const bool bn_ok = bn < N;
+  const TB* brow = BT ? B + (long long)(bn_ok ? bn : N - 1) * ldb : nullptr;
+  const bool bvec = !BT && bn + EB <= N;    // NN: this thread's EB columns all inside
+
+  struct Stage {
+    V a[EA], b[EB];
+    double s[PRE ? EA : 1];
+  };
+  auto load = [&](int k0, Stage& q) {
+    if (k0 + BK <= K) {  // full slice: runs of consecutive k (A, BT) or n (NN) as vectors
+      ldv<EA>(arow + k0 + ak, q.a);
+      if (PRE) ldv<EA>(srow + k0 + ak, q.s);
+      if (BT) {
+        ldv<EB>(brow + k0 + bc, q.b);
+      } else {
+        const TB* bp = B + (long long)(k0 + br) * ldb;
+        if (bvec) {
+          ldv<EB>(bp + bn, q.b);
+        } else {
+#pragma unroll
+          for (int j = 0; j < EB; ++j) q.b[j] = (V)bp[bn + j < N ? bn + j : N - 1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EA; ++j) {
+        const int k = k0 + ak + j < K ? k0 + ak + j : K - 1;
+        q.a[j] = (V)arow[k];
+        if (PRE) q.s[j] = srow[k];
+      }
+      if (BT) {
+#pragma unroll
+        for (int j = 0; j < EB; ++j) q.b[j] = (V)brow[k0 + bc + j < K ? k0 + bc + j : K - 1];
+      } else {
+        const TB* bp = B + (long long)(k0 + br < K ? k0 + br : K - 1) * ldb;
+#pragma unroll
+        for (int j = 0; j < EB; ++j) q.b[j] = (V)bp[bn + j < N ? bn + j : N - 1];
+      }
+    }
+  };
+  // zero what lies outside the matrices, then write the slice to LDS
+  auto store = [&](int buf, int k0, const Stage& q) {
+    V* as = As + buf * BK * LA;
+    V* bs = Bs + buf * BK * LB;
+#pragma unroll
+    for (int j = 0; j < EA; ++j) {
+      V v = q.a[j];
+      if (PRE) v = (V)((double)v * q.s[j]);
+      as[(ak + j) * LA + ar] = (am_ok && k0 + ak + j < K) ? v : V(0);
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      if (BT)
+        bs[(bc + j) * LB + br] = (bn_ok && k0 + bc + j < K) ? q.b[j] : V(0);
+      else
+        bs[br * LB + bc + j] = (k0 + br < K && bn + j < N) ? q.b[j] : V(0);
+    }
+  };
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+    const V* as = As + buf * BK * LA;
+    const V* bs = Bs + buf * BK * LB;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      V a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = as[(ks + grp) * LA + wm0 + i * 16 + col];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = bs[(ks + grp) * LB + wn0 + j * 16 + col];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mma(a[i], b[j], acc[i][j]);
+    }
+  };
+  // slice t is loaded into stage t & 1 and stored to LDS buffer t & 1
+  const int nk = (K + BK - 1) / BK;
+  Stage q0, q1;
+  load(0, q0);
+  store(0, 0, q0);
+  if (nk > 1) load(BK, q1);
+  __syncthreads();
+  // step t: load slice t+2 into stage t&1, compute slice t, store slice t+1
+  auto step = [&](int t, Stage& ql, const Stage& qs) {
+    if (t + 2 < nk) load((t + 2) * BK, ql);
+    compute(t & 1);
+    if (t + 1 < nk) store((t + 1) & 1, (t + 1) * BK, qs);
+    __syncthreads();
+  };
+  int t = 0;
+  for (; t + 1 < nk; t += 2) {
+    step(t, q0, q1);
+    step(t + 1, q1, q0);
+  }
+  if (t < nk) step(t, q0, q1);
+
+  double dot = 0.0;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = tm0 + wm0 + i * 16 + (G::ROW_STRIDE4 ? grp + 4 * r : 4 * grp + r);
+        const int n = tn0 + wn0 + j * 16 + col;
+        if (m < M && n < N) {
+          double v = (double)acc[i][j][r];
+          const long long c = (long long)m * ldc + n;
+          if (ep.lrow) v /= ep.lrow[m] + ep.lcol[n];
+          if (ep.Sc) v *= ep.Sc[c];
+          C[c] = (TC)v;
+          if (ep.partial) dot += ep.rdot[c] * v;
+        }
+      }
+  if (ep.partial) {
+    const double sum = block_sum(dot);
+    if (threadIdx.x == 0) ep.partial[blockIdx.x] = sum;
+  }
+}
+
+struct Cfg {
+  int tm, tn;
+};
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+// The largest tile (fewer re-reads of A and B) that still gives two blocks
+// per CU, within 64 KB of LDS; else the smallest.  The choice does not depend
+// on the precision, so the number of blocks of the last product (which carry
+// the (r, s) partials) is known from the shape alone.  IGAFD_GEMM_TILE=<tm>x<tn>
+// overrides it (tuning).
+Cfg pick(int M, int N) {
+  if (const char* e = std::getenv("IGAFD_GEMM_TILE")) {
+    const int tm = std::atoi(e), tn = std::strchr(e, 'x') ? std::atoi(std::strchr(e, 'x') + 1) : 0;
+    if ((tm == 2 || tm == 4) && (tn == 2 || tn == 4) && !(tm == 4 && tn == 4)) return {tm, tn};
+  }
+  const Cfg cand[4] = {{4, 4}, {4, 2}, {2, 4}, {2, 2}};
+  const long long want = 2LL * device_cus();
+  for (const Cfg& g : cand) {
+    const size_t lds = sizeof(double) * 2 * kBK * ((2 * g.tm * 16 + kPad) + (2 * g.tn * 16 + kPad));
+    if (lds > 64 * 1024) continue;
+    const long long tiles = (long long)((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
+    if (tiles >= want) return g;
+  }
+  return {2, 2};
+}
+
+int grid_of(int M, int N, Cfg g) {
+  const int tiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
+  return 8 * ((tiles + 7) / 8);
+}
+
+template <class G, bool BT, typename TA, typename TB, typename TC>
+igafd_status launch(hipStream_t st, const TA* A, long long lda, const TB* B, long long ldb, TC* C, long long ldc, int M,
+                    int N, int K, const GEpi& ep) {
+  using V = typename G::V;
+  const Cfg g = pick(M, N);
+  const int tiles_n = (N + 32 * g.tn - 1) / (32 * g.tn);
+  const int ntiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * tiles_n;
+  const dim3 grid((unsigned)grid_of(M, N, g));
+#define IGAFD_G(TM, TN)                                                                                         \
+  if (g.tm == TM && g.tn == TN) {                                                                               \
+    constexpr size_t lds = lds_bytes<TM, TN, V>();                                                              \
+    if (ep.Sa)                                                                                                  \
+      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, true, TA, TB, TC>), grid, dim3(kBlock), lds, st, A, lda, B, ldb, \
+                         C, ldc, M, N, K, tiles_n, ntiles, ep);                                                \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, false, TA, TB, TC>), grid, dim3(kBlock), lds, st, A, lda, B,     \
+                         ldb, C, ldc, M, N, K, tiles_n, ntiles, ep);                                           \
+    IGAFD_HIP_CHECK(hipGetLastError());                                                                         \
+    return IGAFD_OK;                                                                                            \
+  }
+  IGAFD_G(4, 4) IGAFD_G(4, 2) IGAFD_G(2, 4) IGAFD_G(2, 2)
+#undef IGAFD_G
+  set_error("internal: bad product tile");
+  return IGAFD_ERR_ARG;
+}
+
+template <class G>
+const typename G::V* wm(const DevDir& d, int which);
+template <>
+const double* wm<G64>(const DevDir& d, int which) { return d.W64[which]; }
+template <>
+const float* wm<G32>(const DevDir& d, int which) { return d.W32[which]; }
+
+// T: intermediate type (double for FP64, float for FP32)
+template <class G, typename T>
+igafd_status apply2d(igafd_ctx* c, const double* r, double* s, const double* S, double* partial, const int* flag,
+                     int ldr, int lds) {
+  using V = typename G::V;
+  const DevDir* d = c->ddir;
+  const int n1 = c->n[0], n2 = c->n[1];
+  if (ldr <= 0) ldr = n1;
+  if (lds <= 0) lds = n1;
+  T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
+  T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
+  const hipStream_t st = c->stream;
+  GEpi e1, e2, e3, e4;
+  e1.flag = e2.flag = e3.flag = e4.flag = flag;
+  e1.Sa = S;
+  e2.lrow = d[1].lam;
+  e2.lcol = d[0].lam;
+  e4.Sc = S;
+  if (partial) {
+    if (fd_gemm_blocks(c) > c->npartial) {
+      set_error("internal: FD grid larger than the partial-sum buffer");
+      return IGAFD_ERR_ARG;
+    }
+    e4.rdot = r;
+    e4.partial = partial;
+  }
+  igafd_status stt;
+  // T = R U1: C[i2][k1] = sum_i1 R[i2][i1] W1f[k1][i1]
+  if ((stt = launch<G, true, double, V, T>(st, r, ldr, wm<G>(d[0], 0), d[0].npad, b0, n1, n2, n1, n1, e1)) != IGAFD_OK)
+    return stt;
+  // Y = (U2^T T) / (lam2[k2] + lam1[k1])
+  if ((stt = launch<G, false, V, T, T>(st, wm<G>(d[1], 0), d[1].npad, b0, n1, b1, n1, n2, n1, n2, e2)) != IGAFD_OK)
+    return stt;
+  // Z = U2 Y
+  if ((stt = launch<G, false, V, T, T>(st, wm<G>(d[1], 1), d[1].npad, b1, n1, b0, n1, n2, n1, n2, e3)) != IGAFD_OK)
+    return stt;
+  // S = Z U1^T: C[i2][i1] = sum_k1 Z[i2][k1] W1b[i1][k1]
+  return launch<G, true, T, V, double>(st, b0, n1, wm<G>(d[0], 1), d[0].npad, s, lds, n2, n1, n1, e4);
+}
+
+}  // namespace
+
+int fd_gemm_blocks(const igafd_ctx* c) { return grid_of(c->n[1], c->n[0], pick(c->n[1], c->n[0])); }
+
+igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
+                             const int* flag, int ldr, int lds) {
+  if (c->dim != 2) {
+    set_error("internal: tiled products are for 2D grids");
+    return IGAFD_ERR_ARG;
+  }
+  switch (prec) {
+    case IGAFD_FP64:
+      return apply2d<G64, double>(c, r, s, S, partial, flag, ldr, lds);
+    case IGAFD_FP32:
+      return apply2d<G32, float>(c, r, s, S, partial, flag, ldr, lds);
+    default:
+      set_error("internal: tiled products run in FP64 or FP32");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+}  // namespace igafd

@@ -147,4 +147,9 @@ int fd_dot_blocks(const igafd_ctx* c, int prec);
 int fd_dot_blocks_max(const igafd_ctx* c);
 int fd_npad(int n);
 bool fd_fused_ok(const igafd_ctx* c);
+// gemm.hip: 2D apply by tiled products (prec FP64 or FP32); r and s may be
+// sub-blocks of wider grids (row strides ldr, lds; 0 = n1)
+igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
+                             double* partial_rz, const int* flag, int ldr, int lds);
+int fd_gemm_blocks(const igafd_ctx* c);  // blocks (= (r, s) partials) of the last product
 }  // namespace igafd
