@@ -28,10 +28,12 @@ def hipcc() -> str:
 
 
 # extra flags per source file
+_VGPR_MFMA = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 PER_FILE_FLAGS = {
-    # MFMA accumulators in VGPRs: in AGPRs the compiler copied every accumulator
-    # between the register files on each K slice of the tiled products
-    "gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    # MFMA accumulators in VGPRs: in AGPRs the compiler copied the accumulators
+    # between the register files inside the contraction loops
+    "gemm.hip": _VGPR_MFMA,
+    "fd.hip": _VGPR_MFMA,
 }
 
 
