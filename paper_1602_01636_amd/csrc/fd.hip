@@ -819,10 +819,16 @@ igafd_status schwarz(igafd_ctx* c, const double* r, double* s, double* partial, 
     return IGAFD_ERR_ARG;
   }
   s1->fd_tiles = s2->fd_tiles = c->fd_tiles;
-  igafd_status st = apply<Pr, T>(s2, r, s, nullptr, nullptr, flag, n, n);
-  if (st != IGAFD_OK) return st;
-  st = apply<Pr, T>(s1, r, c->fdbuf[0], nullptr, nullptr, flag, n, h);
-  if (st != IGAFD_OK) return st;
+  igafd_status st;
+  constexpr int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
+  if (prec != IGAFD_BF16 && use_gemm(s1, prec) && use_gemm(s2, prec)) {
+    // both subdomain applies by tiled products, each pass of the two in one launch
+    st = fd_apply_gemm2d_pair(prec, s2, r, n, s, n, s1, r, n, c->fdbuf[0], h, flag);
+    if (st != IGAFD_OK) return st;
+  } else {
+    if ((st = apply<Pr, T>(s2, r, s, nullptr, nullptr, flag, n, n)) != IGAFD_OK) return st;
+    if ((st = apply<Pr, T>(s1, r, c->fdbuf[0], nullptr, nullptr, flag, n, h)) != IGAFD_OK) return st;
+  }
   hipLaunchKernelGGL(k_schwarz_combine, dim3((unsigned)schwarz_blocks(c)), dim3(kBlock), 0, c->stream, c->fdbuf[0], s,
                      r, n, h, c->N, partial, flag);
   IGAFD_HIP_CHECK(hipGetLastError());

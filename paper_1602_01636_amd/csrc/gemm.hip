@@ -71,6 +71,21 @@ struct GEpi {
   const int* flag = nullptr;     // CG stop flag: nonzero -> the launch is a no-op
 };
 
+// One product C = A op(B); a launch runs one or two of them (the two
+// subdomains of the Schwarz apply share each pass: twice the tiles per launch
+// evens out the work per CU)
+template <typename TA, typename TB, typename TC>
+struct GProb {
+  const TA* A;
+  long long lda;
+  const TB* B;
+  long long ldb;
+  TC* C;
+  long long ldc;
+  int M, N, K, tiles_n, ntiles;
+  GEpi ep;
+};
+
 template <int TM, int TN, typename V>
 constexpr size_t lds_bytes() {
   return sizeof(V) * 2 * kBK * ((2 * TM * 16 + kPad) + (2 * TN * 16 + kPad));
@@ -102,9 +117,17 @@ __device__ inline void ldv(const T* p, V* o) {
 
 // PRE: A is scaled by ep.Sa (the input scaling of S P^-1 S)
 template <class G, int TM, int TN, bool BT, bool PRE, typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(kBlock) void k_gemm(const TA* __restrict__ A, long long lda, const TB* __restrict__ B,
-                                                 long long ldb, TC* __restrict__ C, long long ldc, int M, int N,
-                                                 int K, int tiles_n, int ntiles, GEpi ep) {
+__global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA, TB, TC> p1, int grid0) {
+  // blocks [0, grid0) work on p0, the rest on p1 (uniform per block)
+  const bool second = (int)blockIdx.x >= grid0;
+  const int bid = second ? (int)blockIdx.x - grid0 : (int)blockIdx.x;
+  const TA* __restrict__ A = second ? p1.A : p0.A;
+  const TB* __restrict__ B = second ? p1.B : p0.B;
+  TC* __restrict__ C = second ? p1.C : p0.C;
+  const long long lda = second ? p1.lda : p0.lda, ldb = second ? p1.ldb : p0.ldb, ldc = second ? p1.ldc : p0.ldc;
+  const int M = second ? p1.M : p0.M, N = second ? p1.N : p0.N, K = second ? p1.K : p0.K;
+  const int tiles_n = second ? p1.tiles_n : p0.tiles_n, ntiles = second ? p1.ntiles : p0.ntiles;
+  const GEpi ep = second ? p1.ep : p0.ep;
   using V = typename G::V;
   using acc_t = typename G::acc;
   constexpr int BM = 2 * TM * 16, BN = 2 * TN * 16, BK = kBK;
@@ -117,9 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const TA* __restrict__ A, long 
   V* Bs = As + 2 * BK * LA;           // [2][BK][LB]
   if (ep.flag && *ep.flag) return;
   const int per = (ntiles + 7) / 8;
-  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int tile = (bid & 7) * per + (bid >> 3);
   if (tile >= ntiles) {
-    if (ep.partial && threadIdx.x == 0) ep.partial[blockIdx.x] = 0.0;
+    if (ep.partial && threadIdx.x == 0) ep.partial[bid] = 0.0;
     return;
   }
   const int tm0 = (tile / tiles_n) * BM, tn0 = (tile % tiles_n) * BN;
@@ -255,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const TA* __restrict__ A, long 
       }
   if (ep.partial) {
     const double sum = block_sum(dot);
-    if (threadIdx.x == 0) ep.partial[blockIdx.x] = sum;
+    if (threadIdx.x == 0) ep.partial[bid] = sum;
   }
 }
 
@@ -274,25 +297,34 @@ int device_cus() {
   return cus;
 }
 
-// The largest tile (fewer re-reads of A and B) that still gives two blocks
-// per CU, within 64 KB of LDS; else the smallest.  The choice does not depend
-// on the precision, so the number of blocks of the last product (which carry
-// the (r, s) partials) is known from the shape alone.  IGAFD_GEMM_TILE=<tm>x<tn>
+// Tile shape: the one with the least work on the busiest CU, estimated as
+// ceil(tiles / CUs) x tile area (tiles are dealt evenly, all take the same
+// time), among the shapes whose LDS fits 64 KB; ties go to the larger tile
+// (fewer re-reads of A and B).  The choice does not depend on the precision,
+// so the number of blocks of the last product (which carry the (r, s)
+// partials) is known from the shape alone.  IGAFD_GEMM_TILE=<tm>x<tn>
 // overrides it (tuning).
-Cfg pick(int M, int N) {
+Cfg pick(int M, int N, int M1 = 0, int N1 = 0) {
   if (const char* e = std::getenv("IGAFD_GEMM_TILE")) {
     const int tm = std::atoi(e), tn = std::strchr(e, 'x') ? std::atoi(std::strchr(e, 'x') + 1) : 0;
     if ((tm == 2 || tm == 4) && (tn == 2 || tn == 4) && !(tm == 4 && tn == 4)) return {tm, tn};
   }
   const Cfg cand[4] = {{4, 4}, {4, 2}, {2, 4}, {2, 2}};
-  const long long want = 2LL * device_cus();
+  const long long cus = device_cus();
+  Cfg best{2, 2};
+  long long best_cost = -1;
   for (const Cfg& g : cand) {
     const size_t lds = sizeof(double) * 2 * kBK * ((2 * g.tm * 16 + kPad) + (2 * g.tn * 16 + kPad));
     if (lds > 64 * 1024) continue;
-    const long long tiles = (long long)((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
-    if (tiles >= want) return g;
+    long long tiles = (long long)((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
+    if (M1 > 0) tiles += (long long)((M1 + 32 * g.tm - 1) / (32 * g.tm)) * ((N1 + 32 * g.tn - 1) / (32 * g.tn));
+    const long long cost = (tiles + cus - 1) / cus * (32LL * g.tm) * (32LL * g.tn);
+    if (best_cost < 0 || cost < best_cost) {  // candidates run from large to small tiles
+      best_cost = cost;
+      best = g;
+    }
   }
-  return {2, 2};
+  return best;
 }
 
 int grid_of(int M, int N, Cfg g) {
@@ -300,23 +332,27 @@ int grid_of(int M, int N, Cfg g) {
   return 8 * ((tiles + 7) / 8);
 }
 
+// Launch one product, or two sharing a launch (q1 == nullptr: one).
 template <class G, bool BT, typename TA, typename TB, typename TC>
-igafd_status launch(hipStream_t st, const TA* A, long long lda, const TB* B, long long ldb, TC* C, long long ldc, int M,
-                    int N, int K, const GEpi& ep) {
+igafd_status launch(hipStream_t st, GProb<TA, TB, TC> q0, const GProb<TA, TB, TC>* q1) {
   using V = typename G::V;
-  const Cfg g = pick(M, N);
-  const int tiles_n = (N + 32 * g.tn - 1) / (32 * g.tn);
-  const int ntiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * tiles_n;
-  const dim3 grid((unsigned)grid_of(M, N, g));
+  const Cfg g = q1 ? pick(q0.M, q0.N, q1->M, q1->N) : pick(q0.M, q0.N);
+  auto shape = [&](GProb<TA, TB, TC>& q) {
+    q.tiles_n = (q.N + 32 * g.tn - 1) / (32 * g.tn);
+    q.ntiles = ((q.M + 32 * g.tm - 1) / (32 * g.tm)) * q.tiles_n;
+  };
+  shape(q0);
+  GProb<TA, TB, TC> p1 = q1 ? *q1 : q0;
+  shape(p1);
+  const int grid0 = grid_of(q0.M, q0.N, g);
+  const dim3 grid((unsigned)(grid0 + (q1 ? grid_of(p1.M, p1.N, g) : 0)));
 #define IGAFD_G(TM, TN)                                                                                         \
   if (g.tm == TM && g.tn == TN) {                                                                               \
     constexpr size_t lds = lds_bytes<TM, TN, V>();                                                              \
-    if (ep.Sa)                                                                                                  \
-      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, true, TA, TB, TC>), grid, dim3(kBlock), lds, st, A, lda, B, ldb, \
-                         C, ldc, M, N, K, tiles_n, ntiles, ep);                                                \
+    if (q0.ep.Sa || p1.ep.Sa)                                                                                   \
+      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, true, TA, TB, TC>), grid, dim3(kBlock), lds, st, q0, p1, grid0); \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, false, TA, TB, TC>), grid, dim3(kBlock), lds, st, A, lda, B,     \
-                         ldb, C, ldc, M, N, K, tiles_n, ntiles, ep);                                           \
+      hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, false, TA, TB, TC>), grid, dim3(kBlock), lds, st, q0, p1, grid0); \
     IGAFD_HIP_CHECK(hipGetLastError());                                                                         \
     return IGAFD_OK;                                                                                            \
   }
@@ -326,6 +362,23 @@ igafd_status launch(hipStream_t st, const TA* A, long long lda, const TB* B, lon
   return IGAFD_ERR_ARG;
 }
 
+template <typename TA, typename TB, typename TC>
+GProb<TA, TB, TC> prob(const TA* A, long long lda, const TB* B, long long ldb, TC* C, long long ldc, int M, int N,
+                       int K, const GEpi& ep) {
+  GProb<TA, TB, TC> q{};
+  q.A = A;
+  q.lda = lda;
+  q.B = B;
+  q.ldb = ldb;
+  q.C = C;
+  q.ldc = ldc;
+  q.M = M;
+  q.N = N;
+  q.K = K;
+  q.ep = ep;
+  return q;
+}
+
 template <class G>
 const typename G::V* wm(const DevDir& d, int which);
 template <>
@@ -333,44 +386,62 @@ const double* wm<G64>(const DevDir& d, int which) { return d.W64[which]; }
 template <>
 const float* wm<G32>(const DevDir& d, int which) { return d.W32[which]; }
 
-// T: intermediate type (double for FP64, float for FP32)
+// One 2D FD apply (Sec. 4.1 Alg. 1) by four products, or two independent
+// ones (contexts c and c1, same precision) whose four passes share launches.
+// T: intermediate type (double for FP64, float for FP32).
+struct Job {
+  igafd_ctx* c;
+  const double* r;
+  double* s;
+  int ldr, lds;
+};
+
 template <class G, typename T>
-igafd_status apply2d(igafd_ctx* c, const double* r, double* s, const double* S, double* partial, const int* flag,
-                     int ldr, int lds) {
+igafd_status apply2d(const Job* jobs, int count, const double* S, double* partial, const int* flag) {
   using V = typename G::V;
-  const DevDir* d = c->ddir;
-  const int n1 = c->n[0], n2 = c->n[1];
-  if (ldr <= 0) ldr = n1;
-  if (lds <= 0) lds = n1;
-  T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
-  T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
-  const hipStream_t st = c->stream;
-  GEpi e1, e2, e3, e4;
-  e1.flag = e2.flag = e3.flag = e4.flag = flag;
-  e1.Sa = S;
-  e2.lrow = d[1].lam;
-  e2.lcol = d[0].lam;
-  e4.Sc = S;
-  if (partial) {
-    if (fd_gemm_blocks(c) > c->npartial) {
-      set_error("internal: FD grid larger than the partial-sum buffer");
-      return IGAFD_ERR_ARG;
+  using P1 = GProb<double, V, T>;
+  using P2 = GProb<V, T, T>;
+  using P4 = GProb<T, V, double>;
+  P1 a1[2];
+  P2 a2[2], a3[2];
+  P4 a4[2];
+  for (int j = 0; j < count; ++j) {
+    igafd_ctx* c = jobs[j].c;
+    const DevDir* d = c->ddir;
+    const int n1 = c->n[0], n2 = c->n[1];
+    const int ldr = jobs[j].ldr > 0 ? jobs[j].ldr : n1, lds = jobs[j].lds > 0 ? jobs[j].lds : n1;
+    T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
+    T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
+    GEpi e1, e2, e3, e4;
+    e1.flag = e2.flag = e3.flag = e4.flag = flag;
+    e1.Sa = S;
+    e2.lrow = d[1].lam;
+    e2.lcol = d[0].lam;
+    e4.Sc = S;
+    if (partial) {
+      if (count != 1 || fd_gemm_blocks(c) > c->npartial) {
+        set_error("internal: FD grid larger than the partial-sum buffer");
+        return IGAFD_ERR_ARG;
+      }
+      e4.rdot = jobs[j].r;
+      e4.partial = partial;
     }
-    e4.rdot = r;
-    e4.partial = partial;
+    // T = R U1: C[i2][k1] = sum_i1 R[i2][i1] W1f[k1][i1]
+    a1[j] = prob(jobs[j].r, ldr, wm<G>(d[0], 0), d[0].npad, b0, n1, n2, n1, n1, e1);
+    // Y = (U2^T T) / (lam2[k2] + lam1[k1])
+    a2[j] = prob(wm<G>(d[1], 0), d[1].npad, (const T*)b0, n1, b1, n1, n2, n1, n2, e2);
+    // Z = U2 Y
+    a3[j] = prob(wm<G>(d[1], 1), d[1].npad, (const T*)b1, n1, b0, n1, n2, n1, n2, e3);
+    // S = Z U1^T: C[i2][i1] = sum_k1 Z[i2][k1] W1b[i1][k1]
+    a4[j] = prob((const T*)b0, n1, wm<G>(d[0], 1), d[0].npad, jobs[j].s, lds, n2, n1, n1, e4);
   }
+  const hipStream_t st = jobs[0].c->stream;
+  const bool two = count == 2;
   igafd_status stt;
-  // T = R U1: C[i2][k1] = sum_i1 R[i2][i1] W1f[k1][i1]
-  if ((stt = launch<G, true, double, V, T>(st, r, ldr, wm<G>(d[0], 0), d[0].npad, b0, n1, n2, n1, n1, e1)) != IGAFD_OK)
-    return stt;
-  // Y = (U2^T T) / (lam2[k2] + lam1[k1])
-  if ((stt = launch<G, false, V, T, T>(st, wm<G>(d[1], 0), d[1].npad, b0, n1, b1, n1, n2, n1, n2, e2)) != IGAFD_OK)
-    return stt;
-  // Z = U2 Y
-  if ((stt = launch<G, false, V, T, T>(st, wm<G>(d[1], 1), d[1].npad, b1, n1, b0, n1, n2, n1, n2, e3)) != IGAFD_OK)
-    return stt;
-  // S = Z U1^T: C[i2][i1] = sum_k1 Z[i2][k1] W1b[i1][k1]
-  return launch<G, true, T, V, double>(st, b0, n1, wm<G>(d[0], 1), d[0].npad, s, lds, n2, n1, n1, e4);
+  if ((stt = launch<G, true>(st, a1[0], two ? &a1[1] : nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, a2[0], two ? &a2[1] : nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, a3[0], two ? &a3[1] : nullptr)) != IGAFD_OK) return stt;
+  return launch<G, true>(st, a4[0], two ? &a4[1] : nullptr);
 }
 
 }  // namespace
@@ -383,11 +454,30 @@ igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s,
     set_error("internal: tiled products are for 2D grids");
     return IGAFD_ERR_ARG;
   }
+  const Job job{c, r, s, ldr, lds};
   switch (prec) {
     case IGAFD_FP64:
-      return apply2d<G64, double>(c, r, s, S, partial, flag, ldr, lds);
+      return apply2d<G64, double>(&job, 1, S, partial, flag);
     case IGAFD_FP32:
-      return apply2d<G32, float>(c, r, s, S, partial, flag, ldr, lds);
+      return apply2d<G32, float>(&job, 1, S, partial, flag);
+    default:
+      set_error("internal: tiled products run in FP64 or FP32");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int ldr0, double* s0, int lds0,
+                                  igafd_ctx* c1, const double* r1, int ldr1, double* s1, int lds1, const int* flag) {
+  if (c0->dim != 2 || c1->dim != 2 || c0->stream != c1->stream) {
+    set_error("internal: paired tiled products need two 2D contexts on one stream");
+    return IGAFD_ERR_ARG;
+  }
+  const Job jobs[2] = {{c0, r0, s0, ldr0, lds0}, {c1, r1, s1, ldr1, lds1}};
+  switch (prec) {
+    case IGAFD_FP64:
+      return apply2d<G64, double>(jobs, 2, nullptr, nullptr, flag);
+    case IGAFD_FP32:
+      return apply2d<G32, float>(jobs, 2, nullptr, nullptr, flag);
     default:
       set_error("internal: tiled products run in FP64 or FP32");
       return IGAFD_ERR_ARG;

@@ -152,4 +152,7 @@ bool fd_fused_ok(const igafd_ctx* c);
 igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                              double* partial_rz, const int* flag, int ldr, int lds);
 int fd_gemm_blocks(const igafd_ctx* c);  // blocks (= (r, s) partials) of the last product
+// two independent 2D applies (no scaling, no partials) whose passes share launches
+igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int ldr0, double* s0, int lds0,
+                                  igafd_ctx* c1, const double* r1, int ldr1, double* s1, int lds1, const int* flag);
 }  // namespace igafd
