@@ -23,6 +23,8 @@ Modules
                 apply of P^-1 (Sec. 4.1 Alg. 1, Sec. 5.1 Alg. 3), the
                 explicit Kronecker form of P (Sec. 3 eq. prec)
     pcg         preconditioned CG, flexible CG, scaled preconditioner
+    adi         three-variable ADI of Douglas as an inexact P^-1 (Sec. 5.2
+                Alg. '3D ADI method'), its parameters and closed form
     multipatch  L-shaped three-patch domain with C^0 interfaces and the
                 overlapping additive Schwarz preconditioners P_EAS, P_IAS
                 (Sec. 6 eq. Peas, eq. Pias)

@@ -1,0 +1,105 @@
+"""Pins of the three-variable ADI oracle (Sec. 5.2 eq. ADI3D, eq. ADI3D2,
+Alg. '3D ADI method'; Sec. 4.2 Thm. ADIprec): the steps of the algorithm
+against the closed form in the FD eigenbasis, the error factor against the
+scalar Douglas recursion of eq. ADI3D, the error bound rho_J = ||T_J||, the
+preconditioner's symmetry and the condition-number bound of Thm. ADIprec,
+and the parameter rule."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import adi, assembly, fd
+
+CASES = [
+    ("uniform_p2", synth.uniform_problem(3, [6, 7, 5], 2)),
+    ("jittered_p3", synth.make_problem(3, 3, [synth.jittered_knots(E, 3, 20 + E) for E in (8, 6, 7)])),
+    ("uniform_p5", synth.uniform_problem(3, [4, 5, 6], 5)),
+]
+IDS = [c[0] for c in CASES]
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=IDS)
+def test_algorithm_equals_closed_form(name, prob):
+    F = fd.setup(prob)
+    w, r, J0 = adi.parameters(F, 0.1)
+    x = synth.random_vector(int(np.prod([len(f["lam"]) for f in F])), 5)
+    for om in (w, w[::-1], np.array([3.0, 50.0, 7.5])):
+        s1 = adi.apply(F, x, om)
+        s2 = adi.closed_form(F, x, om)
+        assert np.linalg.norm(s1 - s2) <= 1e-12 * np.linalg.norm(s2)
+
+
+def test_error_factor_is_the_scalar_douglas_recursion():
+    # eq. ADI3D with commuting scalars (M = 1, K_d = l_d): the error after one
+    # step, divided by the error before it
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        l1, l2, l3 = rng.uniform(0.5, 200.0, 3)
+        om = rng.uniform(0.5, 200.0)
+        lam = l1 + l2 + l3
+        e0 = 1.0
+        e1 = -(l1 + 2 * l2 + 2 * l3 - om) * e0 / (l1 + om)
+        e2 = (l2 * e0 + om * e1) / (l2 + om)
+        e3 = (l3 * e0 + om * e2) / (l3 + om)
+        # same through the solution iterates, r = lam * s
+        s_ex, s0 = 0.7, 0.0
+        r = lam * s_ex
+        s1 = (2 * r - (l1 + 2 * l2 + 2 * l3 - om) * s0) / (l1 + om)
+        s2 = (l2 * s0 + om * s1) / (l2 + om)
+        s3 = (l3 * s0 + om * s2) / (l3 + om)
+        g = adi.error_factor([om], l1, l2, l3)
+        assert abs(e3 - g) <= 1e-13 and abs((s3 - s_ex) / (s0 - s_ex) - g) <= 1e-12
+
+
+def test_rho_is_the_M_norm_contraction():
+    prob = CASES[0][1]
+    F = fd.setup(prob)
+    w, r, _ = adi.parameters(F, 0.1)
+    M = np.kron(F[2]["M"], np.kron(F[1]["M"], F[0]["M"]))     # M3 x M2 x M1
+    lams = [f["lam"] for f in F]
+    # random right-hand sides: ||s - s_J||_M <= rho ||s||_M (eq. ADIerr with e_0 = s)
+    for seed in range(5):
+        x = synth.random_vector(M.shape[0], 40 + seed)
+        s = fd.fd_apply(F, x)
+        e = s - adi.apply(F, x, w)
+        assert math.sqrt(e @ M @ e) <= r * math.sqrt(s @ M @ s) * (1 + 1e-10)
+    # equality on the eigenvector of the worst triple
+    G = np.abs(adi.error_factor(w, lams[0][None, None, :], lams[1][None, :, None], lams[2][:, None, None]))
+    k3, k2, k1 = np.unravel_index(np.argmax(G), G.shape)
+    vec = np.kron(F[2]["U"][:, k3], np.kron(F[1]["U"][:, k2], F[0]["U"][:, k1]))
+    x = fd.kron_P(F) @ vec                      # so that s = P^-1 x = vec
+    e = vec - adi.apply(F, x, w)
+    assert abs(math.sqrt(e @ M @ e) / math.sqrt(vec @ M @ vec) - r) <= 1e-10
+
+
+def test_preconditioner_spd_and_condition_bound():
+    """Thm. ADIprec: P_J is SPD and kappa(P_J^-1 A) <= (1+eps)/(1-eps) kappa(P^-1 A)."""
+    prob = synth.uniform_problem(3, [4, 5, 3], 2, geometry={"kind": "ring"})
+    F = fd.setup(prob)
+    eps = 0.1
+    w, r, _ = adi.parameters(F, eps)
+    N = int(np.prod([len(f["lam"]) for f in F]))
+    PJ = np.column_stack([adi.apply(F, e, w) for e in np.eye(N)])
+    assert np.abs(PJ - PJ.T).max() <= 1e-12 * np.abs(PJ).max()
+    assert np.linalg.eigvalsh(0.5 * (PJ + PJ.T)).min() > 0
+    A = assembly.assemble_matrix(prob).toarray()
+    P = fd.kron_P(F)
+    ep = sla.eigh(A, P, eigvals_only=True)
+    ej = np.sort(np.real(np.linalg.eigvals(PJ @ A)))
+    assert ej.max() / ej.min() <= (1 + eps) / (1 - eps) * ep.max() / ep.min() * (1 + 1e-10)
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=IDS)
+def test_parameter_rule(name, prob):
+    F = fd.setup(prob)
+    eps = 0.1
+    w, r, J0 = adi.parameters(F, eps)
+    a, b = adi.spectrum_interval(F)
+    assert J0 == math.ceil(1.16 * math.log(b / a) * math.log(1 / eps))
+    assert 1 <= len(w) <= J0 and r <= eps
+    assert np.all(np.diff(w) > 0) and abs(w[0] - a) <= 1e-12 * a and abs(w[-1] - b) <= 1e-12 * b
+    if len(w) > 1:   # the count is the smallest that meets the tolerance
+        assert adi.rho(adi.geometric_parameters(a, b, len(w) - 1), [f["lam"] for f in F]) > eps
