@@ -194,6 +194,28 @@ igafd_status igafd_get_eigen(const igafd_ctx* ctx, int dir, double* U_host, doub
 igafd_status igafd_univariate(int degree, int nknots, const double* knots, int quad,
                               double* M, double* K, double* U, double* lam, int* n_out);
 
+/* ---------------- three-variable ADI (inexact P^-1) ----------------
+ * Sec. 5.2 (eq. ADI3D, Alg. "3D ADI method") and Sec. 4.2 Thm. ADIprec: J
+ * steps of the ADI iteration of Douglas for P s = r from s_0 = 0 give
+ * s_J = P_J^-1 r with P_J symmetric positive definite and
+ * kappa(P_J^-1 A) <= (1 + eps)/(1 - eps) kappa(P^-1 A) when ||T_J|| <= eps.
+ * Parameters: geometric between the smallest and largest eigenvalue a, b of
+ * the M_d^-1 K_d, omega_j = a (b/a)^((j-1)/(J-1)); J the smallest count with
+ * ||T_J|| <= eps (||T_J|| evaluated exactly over the triples of univariate
+ * eigenvalues), at most J0 = ceil(1.16 ln(b/a) ln(1/eps)) (eq. ADI3Diter).
+ */
+
+/* From now on igafd_apply_precond and igafd_solve apply P_J^-1 (FP64 only,
+ * no scaling) instead of the exact fast diagonalisation; eps in (0, 1), or 0
+ * to switch back to FD.  3D single-patch contexts.  Allocates the univariate
+ * bands and factors and 5 N doubles of workspace.  *J (steps) and *rho
+ * (= ||T_J||) are optional host outputs. */
+igafd_status igafd_set_adi(igafd_ctx* ctx, double eps, int* J, double* rho);
+
+/* Parameters in use (all outputs optional, host): J = 0 when ADI is off;
+ * omegas: capacity >= J values. */
+igafd_status igafd_get_adi(const igafd_ctx* ctx, int* J, int* J0, double* rho, double* omegas, int capacity);
+
 /* ---------------- multi-patch: L-shaped domain, additive Schwarz ----------------
  * Sec. 6 (eq. Pias) and the multi-patch experiment of Sec. 7: the L-shaped
  * domain [0,1]^2 without (1/2,1] x (1/2,1], made of three square patches

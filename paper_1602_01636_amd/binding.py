@@ -76,6 +76,9 @@ _SIGNATURES = {
     "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
     "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "igafd_lshape_setup": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "igafd_set_adi": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "igafd_get_adi": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                C.c_void_p, C.c_int]),
     "igafd_lshape_corner": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
     "igafd_scaling_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
     "igafd_set_scaling_diag_ratio": (C.c_int, [C.c_void_p]),
@@ -236,6 +239,23 @@ def igafd_lshape_setup(knots, degree: int, stream=None) -> Context:
     ctx = Context(h, n, N, nnz, bb, 2, int(degree))
     ctx.hole, ctx.ndofs = igafd_lshape_corner(ctx)
     return ctx
+
+
+def igafd_set_adi(ctx, eps):
+    """Switch the preconditioner to J steps of the three-variable ADI with
+    ||T_J|| <= eps (eps = 0: back to FD).  Returns (J, rho)."""
+    J, rho = C.c_int(), C.c_double()
+    _check(lib().igafd_set_adi(_h(ctx), float(eps), C.byref(J), C.byref(rho)))
+    return J.value, rho.value
+
+
+def igafd_get_adi(ctx) -> dict:
+    """{"J", "J0", "rho", "omegas"} of the ADI preconditioner (J = 0: off)."""
+    J, J0, rho = C.c_int(), C.c_int(), C.c_double()
+    _check(lib().igafd_get_adi(_h(ctx), C.byref(J), C.byref(J0), C.byref(rho), None, 0))
+    om = np.zeros(max(J.value, 1))
+    _check(lib().igafd_get_adi(_h(ctx), None, None, None, om.ctypes.data_as(C.c_void_p), len(om)))
+    return {"J": J.value, "J0": J0.value, "rho": rho.value, "omegas": om[: J.value].copy()}
 
 
 def igafd_lshape_corner(ctx):

@@ -457,6 +457,10 @@ igafd_status check_opts(const igafd_ctx* c, const igafd_solve_opts* o) {
     set_error("rtol must be positive");
     return IGAFD_ERR_ARG;
   }
+  if (c->adi && (o->precision != IGAFD_FP64 || o->use_scaling)) {
+    set_error("the ADI preconditioner runs in FP64 and without scaling");
+    return IGAFD_ERR_ARG;
+  }
   if (o->use_scaling && !c->scaling_set) {
     set_error("use_scaling requested but no scaling set");
     return IGAFD_ERR_ARG;
@@ -920,6 +924,7 @@ void igafd_destroy(igafd_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (int k = 0; k < 2; ++k) igafd_destroy(c->sub[k]);
+  adi_free(c);
   for (int l = 0; l < 3; ++l) free_dir(&c->ddir[l]);
   free_dev(c->band);
   free_dev(c->ext);
@@ -990,6 +995,51 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   c->hole = h;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
   *out = c.release();
+  return IGAFD_OK;
+}
+
+igafd_status igafd_set_adi(igafd_ctx* c, double eps, int* J, double* rho) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (eps == 0.0) {
+    adi_free(c);
+    if (J) *J = 0;
+    if (rho) *rho = 0.0;
+    return IGAFD_OK;
+  }
+  if (c->hole >= 0) {
+    set_error("the ADI preconditioner is for single-patch 3D problems");
+    return IGAFD_ERR_ARG;
+  }
+  const igafd_status s = adi_setup(c, eps);
+  if (s != IGAFD_OK) return s;
+  if (J) *J = (int)c->adi->omega.size();
+  if (rho) *rho = c->adi->rho;
+  return IGAFD_OK;
+}
+
+igafd_status igafd_get_adi(const igafd_ctx* c, int* J, int* J0, double* rho, double* omegas, int capacity) {
+  if (!c) {
+    set_error("null context");
+    return IGAFD_ERR_ARG;
+  }
+  if (!c->adi) {
+    if (J) *J = 0;
+    if (J0) *J0 = 0;
+    if (rho) *rho = 0.0;
+    return IGAFD_OK;
+  }
+  const int n = (int)c->adi->omega.size();
+  if (omegas && capacity < n) {
+    set_error("omega array too short");
+    return IGAFD_ERR_ARG;
+  }
+  if (J) *J = n;
+  if (J0) *J0 = c->adi->J0;
+  if (rho) *rho = c->adi->rho;
+  if (omegas) std::memcpy(omegas, c->adi->omega.data(), sizeof(double) * n);
   return IGAFD_OK;
 }
 
@@ -1118,8 +1168,13 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
     set_error("batched solve needs count >= 1 contexts, vectors and options");
     return IGAFD_ERR_ARG;
   }
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (ctxs[i] && is_lshape(ctxs[i], "igafd_solve_batched")) return IGAFD_ERR_ARG;
+    if (ctxs[i] && ctxs[i]->adi) {
+      set_error("igafd_solve_batched runs the FD preconditioner only");
+      return IGAFD_ERR_ARG;
+    }
+  }
   return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
 }
 

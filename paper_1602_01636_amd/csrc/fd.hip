@@ -859,6 +859,7 @@ igafd_status schwarz_apply(igafd_ctx* c, int prec, const double* r, double* s, c
 bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c); }
 
 int fd_dot_blocks(const igafd_ctx* c, int prec) {
+  if (c->adi) return (int)((c->N + kBlock - 1) / kBlock);
   if (c->hole >= 0) return schwarz_blocks(c);
   if (use_gemm(c, prec)) return fd_gemm_blocks(c);
   return (c->fd_fused && fused_ok(c)) ? slice_blocks(c) : dot_blocks_for(c);
@@ -877,6 +878,7 @@ int fd_dot_blocks_max(const igafd_ctx* c) {
 
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
                       const int* flag) {
+  if (c->adi) return adi_apply(c, prec, r, s, S, partial, flag);
   if (c->hole >= 0) return schwarz_apply(c, prec, r, s, S, partial, flag);
   if (c->fd_fused && fused_ok(c)) {
     const DevDir* d = c->ddir;

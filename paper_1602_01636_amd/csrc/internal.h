@@ -79,6 +79,20 @@ enum { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_MAXIT = 3 
 
 }  // namespace igafd
 
+// Three-variable ADI state (adi.hip): parameters and device bands/factors
+struct igafd_adi {
+  double eps = 0.0, rho = 1.0;
+  std::vector<double> omega;
+  int J0 = 0;
+  // device: per direction the bands of K_d and M_d ([n][2p+1], entry (i, i+k-p))
+  // and the lower band Cholesky factors ([n][p+1], entry (i, i-k)) of M_d
+  // (slot 0) and of K_d + omega_j M_d (slot j)
+  double* bandK[3] = {nullptr, nullptr, nullptr};
+  double* bandM[3] = {nullptr, nullptr, nullptr};
+  double* fac[3] = {nullptr, nullptr, nullptr};
+  double* work = nullptr;  // rt, v, u, t1, t2: 5 N doubles
+};
+
 struct igafd_ctx {
   int dim = 0, p = 0;
   int n[3] = {1, 1, 1};
@@ -108,6 +122,7 @@ struct igafd_ctx {
   // sub[0], sub[1]: preconditioner-only contexts of the two Schwarz subdomains
   int hole = -1;
   igafd_ctx* sub[2] = {nullptr, nullptr};
+  igafd_adi* adi = nullptr;                // set: the preconditioner is P_J (three-variable ADI)
   // workspace
   double *r = nullptr, *z = nullptr, *q = nullptr, *zold = nullptr;
   double* pv_pad = nullptr;                // search direction with the band's zero halo
@@ -152,6 +167,11 @@ bool fd_fused_ok(const igafd_ctx* c);
 igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                              double* partial_rz, const int* flag, int ldr, int lds);
 int fd_gemm_blocks(const igafd_ctx* c);  // blocks (= (r, s) partials) of the last product
+// adi.hip
+igafd_status adi_setup(igafd_ctx* c, double eps);
+igafd_status adi_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
+                       double* partial_rz, const int* flag);
+void adi_free(igafd_ctx* c);
 // two independent 2D applies (no scaling, no partials) whose passes share launches
 igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int ldr0, double* s0, int lds0,
                                   igafd_ctx* c1, const double* r1, int ldr1, double* s1, int lds1, const int* flag);
