@@ -20,6 +20,8 @@ Other workloads (--workload), each printing one JSON line of the same form:
   square   2D unit square, identity map, p = 3, 64^2 elements (one iteration: launch latency)
   lshape   L-shaped domain of three square patches with C0 interfaces (Sec. 6, Table L),
            h^-1 = 1024 elements per patch and direction, p = 3: CG + additive Schwarz P_IAS
+  adi      thick ring 128^3, p = 3: CG + the three-variable ADI preconditioner P_J (eps = 0.1)
+           beside CG + the exact FD apply (the paper's FD-vs-ADI comparison)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -501,12 +503,54 @@ def run_lshape(args, api, torch, synth):
     return out
 
 
+def run_adi(args, api, torch, synth):
+    """CG with the three-variable ADI preconditioner P_J (eps = 0.1) beside CG
+    with the exact FD apply, on the thick ring (the paper's FD-vs-ADI
+    comparison of Sec. 7)."""
+    E, p = args.elements or 128, args.degree or 3
+    eps = 0.1
+    ctx = api.igafd_setup(synth.thick_ring(E=E, p=p))
+    b = rhs(api, torch, synth, ctx)
+    u = torch.zeros_like(b)
+    t0 = time.perf_counter()
+    J, rho = api.igafd_set_adi(ctx, eps)
+    t_params = time.perf_counter() - t0
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup)
+    ms_per_step = 1e3 * float(np.median(times))
+    x = torch.randn(ctx.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    t_adi = event_time(torch, lambda: api.igafd_apply_precond(ctx, "fp64", x, y), 10)
+    t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), 20)
+    api.igafd_set_adi(ctx, 0)
+    t_fd = event_time(torch, lambda: api.igafd_apply_precond(ctx, "fp64", x, y), 20)
+    tf, inf = timed_solves(api, torch, ctx, b, u, 3, 1)
+    # bytes one ADI step moves in the kernels as written (vector passes of N doubles):
+    # 2 + 4 (u), 3 + 4 (r*), 4 (s*), 3 + 4 (s**), 3 + 4 (s), 4 (v) = 35 passes
+    by = 35 * 8 * ctx.N * J + 4 * 8 * ctx.N * 2
+    gbs = by / (t_adi * 1e-3) / 1e9
+    log(f"ADI: J = {J}, rho = {rho:.3f}, apply {t_adi * 1e3:.1f} us ({gbs:.0f} GB/s); FD apply {t_fd * 1e3:.1f} us; "
+        f"A product {t_spmv * 1e3:.1f} us")
+    workload = {"workload": f"thick quarter ring, p={p}, {E}^3 elements, N={ctx.N}, CG + three-variable ADI "
+                            f"preconditioner P_J (eps={eps}, J={J})", "elements": E, "degree": p, "N": ctx.N}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"],
+        "adi": {"J": J, "rho": rho, "eps": eps, "param_setup_s": t_params},
+        "fd_comparison": {"ms": 1e3 * float(np.median(tf)), "iters": inf[-1]["iters"]},
+        "kernel_ms": {"adi_apply": t_adi, "fd_apply": t_fd, "spmv": t_spmv},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "P_J apply (banded line products and solves)",
+                     "algorithmic_bytes": by},
+        "cpu_baseline": None})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape"])
+    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape", "adi"])
     ap.add_argument("--elements", type=int, default=0)
     ap.add_argument("--degree", type=int, default=0)
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
@@ -527,7 +571,7 @@ def main():
 
     torch.cuda.set_device(0)
     run = {"ring": run_ring, "warped": run_warped, "batch": run_batch, "learned": run_learned,
-           "square": run_square, "lshape": run_lshape}[args.workload]
+           "square": run_square, "lshape": run_lshape, "adi": run_adi}[args.workload]
     out = run(args, api, torch, synth)
     print(json.dumps(out), flush=True)
 

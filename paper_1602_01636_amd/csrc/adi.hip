@@ -12,10 +12,11 @@
 // so ||T_J|| is evaluated exactly as the largest |prod_j g_j| over the
 // triples of eigenvalues (host, at setup).
 //
-// Device: every step of the algorithm is a banded product or a banded
-// Cholesky solve along one direction of the grid, done by one thread per grid
-// line walking the line with a sliding window of 2p+1 (product) or p
-// (solve) values in registers.  Lines of directions 2 and 3 are taken by
+// Device: every step of the algorithm is a banded product along one direction
+// of the grid (one thread per grid point) or a banded Cholesky solve along one
+// direction (one thread per grid line, walking it in chunks: the next chunk's
+// values load while the recurrence runs on the current one in registers with
+// a window of p values).  Lines of directions 2 and 3 are taken by
 // consecutive threads at consecutive i1, so their loads are coalesced.
 #include <algorithm>
 #include <cmath>
@@ -52,83 +53,262 @@ __device__ inline bool line_of(long long l, int n1, int n2, int n3, long long* b
   return true;
 }
 
-// y = cz z + (ca A + cb B) (x + c2 x2) along direction DIR; A, B bands [n][2P+1].
-// z may be y (each thread reads z_i before writing y_i); x, x2 may not be y.
+constexpr int kLineBlock = 64;  // threads per block of the line solves (few lines: spread over CUs)
+constexpr int kChunk = 16;      // line values loaded together in the solves
+
+// y = cz z + ca B (x + c2 x2) along direction DIR, B a band [n][2P+1]: one
+// thread per grid point (the neighbours along DIR are other threads' points,
+// read through the caches).  z may be y; x and x2 may not.
 template <int P, int DIR>
-__global__ __launch_bounds__(kBlock) void k_line_apply(const double* __restrict__ A, const double* __restrict__ B,
-                                                      double ca, double cb, const double* __restrict__ x,
-                                                      const double* __restrict__ x2, double c2, const double* z,
-                                                      double cz, double* y, int n1, int n2, int n3,
-                                                      const int* __restrict__ flag) {
+__global__ __launch_bounds__(kBlock) void k_band_apply(const double* __restrict__ Bd, double ca,
+                                                      const double* __restrict__ x, const double* __restrict__ x2,
+                                                      double c2, const double* z, double cz, double* y, int n1, int n2,
+                                                      int n3, const int* __restrict__ flag) {
   if (flag && *flag) return;
-  long long base, stride;
-  int len;
-  if (!line_of<DIR>((long long)blockIdx.x * kBlock + threadIdx.x, n1, n2, n3, &base, &stride, &len)) return;
+  const long long N = (long long)n1 * n2 * n3;
+  const long long o = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (o >= N) return;
+  int i, len;
+  long long stride;
+  if (DIR == 0) {
+    i = (int)(o % n1);
+    len = n1;
+    stride = 1;
+  } else if (DIR == 1) {
+    i = (int)((o / n1) % n2);
+    len = n2;
+    stride = n1;
+  } else {
+    i = (int)(o / ((long long)n1 * n2));
+    len = n3;
+    stride = (long long)n1 * n2;
+  }
   constexpr int W = 2 * P + 1;
-  double win[W];  // win[k] = w_{i + k - P}, w = x + c2 x2, zero outside the line
-  auto w_at = [&](int j) -> double {
-    if (j < 0 || j >= len) return 0.0;
-    const long long o = base + (long long)j * stride;
-    return x2 ? x[o] + c2 * x2[o] : x[o];
-  };
+  double acc = 0.0;
 #pragma unroll
-  for (int k = 0; k < W; ++k) win[k] = w_at(k - P);
-  for (int i = 0; i < len; ++i) {
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      double a = 0.0;
-      if (A) a += ca * A[(long long)i * W + k];
-      if (B) a += cb * B[(long long)i * W + k];
-      acc = fma(a, win[k], acc);
+  for (int k = 0; k < W; ++k) {
+    const int j = i + k - P;
+    if (j >= 0 && j < len) {
+      const long long q = o + (long long)(k - P) * stride;
+      const double w = x2 ? x[q] + c2 * x2[q] : x[q];
+      acc = fma(Bd[(long long)i * W + k], w, acc);
     }
-    const long long o = base + (long long)i * stride;
-    y[o] = (z ? cz * z[o] : 0.0) + acc;
+  }
+  y[o] = (z ? cz * z[o] : 0.0) + ca * acc;
+}
+
+// y = (L L^T)^-1 (alpha x) along direction DIR; L lower band [len][P+1] with
+// L[i][k] = L_{i, i-k} for k >= 1 and L[i][0] = 1 / L_{i,i}.  One thread per
+// line.  The factor (the same for every line) is staged in LDS first, so the
+// recurrence reads its coefficients from LDS, not memory; the line is read in
+// chunks of kChunk values, the next chunk's loads issued before the current
+// chunk's recurrence.  len is the (uniform) line length.  In place (x == y)
+// allowed: a chunk is loaded before any of its values is written, and writes
+// never reach a chunk that is still to be loaded.
+template <int P, int DIR>
+__global__ __launch_bounds__(kLineBlock) void k_line_solve(const double* __restrict__ L, double alpha, const double* x,
+                                                          double* y, int n1, int n2, int n3, int len,
+                                                          const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  extern __shared__ double Ls[];  // [len][P+1]
+  constexpr int W = P + 1;
+  for (int e = threadIdx.x; e < len * W; e += kLineBlock) Ls[e] = L[e];
+  __syncthreads();
+  long long base, stride;
+  int len_t;
+  if (!line_of<DIR>((long long)blockIdx.x * kLineBlock + threadIdx.x, n1, n2, n3, &base, &stride, &len_t)) return;
+  const int nch = (len + kChunk - 1) / kChunk;
+  auto ld = [&](const double* src, int i0, double (&b)[kChunk]) {
 #pragma unroll
-    for (int k = 0; k + 1 < W; ++k) win[k] = win[k + 1];
-    win[W - 1] = w_at(i + P + 1);
+    for (int c = 0; c < kChunk; ++c) {
+      const int i = i0 + c < len ? i0 + c : len - 1;
+      b[c] = src[base + (long long)i * stride];
+    }
+  };
+  auto st = [&](int i0, const double (&b)[kChunk]) {
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c)
+      if (i0 + c < len) y[base + (long long)(i0 + c) * stride] = b[c];
+  };
+  double win[P > 0 ? P : 1];  // the last P values (most recent last)
+  double cur[kChunk], nxt[kChunk];
+#pragma unroll
+  for (int k = 0; k < P; ++k) win[k] = 0.0;
+  ld(x, 0, cur);
+  for (int q = 0; q < nch; ++q) {  // forward: L t = alpha x
+    const int i0 = q * kChunk;
+    if (q + 1 < nch) ld(x, i0 + kChunk, nxt);
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int i = i0 + c;
+      if (i < len) {
+        double t = alpha * cur[c];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) t -= Ls[i * W + k] * win[P - k];
+        t *= Ls[i * W];
+        cur[c] = t;
+#pragma unroll
+        for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
+        if (P > 0) win[P - 1] = t;
+      }
+    }
+    st(i0, cur);
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) cur[c] = nxt[c];
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) win[k] = 0.0;
+  ld(y, (nch - 1) * kChunk, cur);
+  for (int q = nch - 1; q >= 0; --q) {  // backward: L^T z = t, chunks from the end
+    const int i0 = q * kChunk;
+    if (q > 0) ld(y, i0 - kChunk, nxt);
+#pragma unroll
+    for (int c = kChunk - 1; c >= 0; --c) {
+      const int i = i0 + c;
+      if (i < len) {
+        double zv = cur[c];
+#pragma unroll
+        for (int k = 1; k <= P; ++k)
+          if (i + k < len) zv -= Ls[(i + k) * W + k] * win[P - k];
+        zv *= Ls[i * W];
+        cur[c] = zv;
+#pragma unroll
+        for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
+        if (P > 0) win[P - 1] = zv;
+      }
+    }
+    st(i0, cur);
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) cur[c] = nxt[c];
   }
 }
 
-// y = (L L^T)^-1 (alpha x) along direction DIR; L lower band [n][P+1] with
-// L[i][k] = L_{i, i-k}.  In place (x == y) allowed.
+// The same solve with the block's 64 lines staged in LDS as a [len][65] tile
+// (element i of the block's line t at i * 65 + t; the odd row length keeps
+// the cooperative reads of direction 1 off a single bank): one read of the
+// lines, both sweeps on the thread's LDS column, one write; lines of up to
+// kLdsLineMax points.
+constexpr int kLdsLineMax = 256;
+constexpr int kTS = kLineBlock + 1;  // row stride of the LDS tile
+
 template <int P, int DIR>
-__global__ __launch_bounds__(kBlock) void k_line_solve(const double* __restrict__ L, double alpha, const double* x,
-                                                      double* y, int n1, int n2, int n3,
-                                                      const int* __restrict__ flag) {
+__global__ __launch_bounds__(kLineBlock) void k_line_solve_lds(const double* __restrict__ L, double alpha,
+                                                              const double* x, double* y, int n1, int n2, int n3,
+                                                              int len, const int* __restrict__ flag) {
   if (flag && *flag) return;
-  long long base, stride;
-  int len;
-  if (!line_of<DIR>((long long)blockIdx.x * kBlock + threadIdx.x, n1, n2, n3, &base, &stride, &len)) return;
+  extern __shared__ double sm[];
   constexpr int W = P + 1;
-  double win[P > 0 ? P : 1];  // the last P values (most recent last)
-#pragma unroll
-  for (int k = 0; k < P; ++k) win[k] = 0.0;
-  for (int i = 0; i < len; ++i) {  // forward: L t = alpha x
-    const long long o = base + (long long)i * stride;
-    double t = alpha * x[o];
-#pragma unroll
-    for (int k = 1; k <= P; ++k) t -= L[(long long)i * W + k] * win[P - k];
-    t /= L[(long long)i * W];
-    y[o] = t;
-#pragma unroll
-    for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
-    if (P > 0) win[P - 1] = t;
+  double* Ls = sm;                      // [len][P+1]
+  double* T = sm + ((len * W + 1) & ~1);  // [len][kTS]
+  for (int e = threadIdx.x; e < len * W; e += kLineBlock) Ls[e] = L[e];
+  const long long l0 = (long long)blockIdx.x * kLineBlock;
+  const long long nlines = DIR == 0 ? (long long)n2 * n3 : DIR == 1 ? (long long)n1 * n3 : (long long)n1 * n2;
+  const int nl = (int)(nlines - l0 < kLineBlock ? nlines - l0 : kLineBlock);
+  // this thread's line (directions 2 and 3: consecutive threads at consecutive i1)
+  long long base = 0, stride = 0;
+  int len_t = 0;
+  const bool mine = line_of<DIR>(l0 + threadIdx.x, n1, n2, n3, &base, &stride, &len_t);
+  if (DIR == 0) {  // the block's lines are contiguous: read them as one run, e = t * len + i
+    const long long b0 = l0 * n1;
+    int t = (int)threadIdx.x / len, i = (int)threadIdx.x % len;
+    for (int e = threadIdx.x; e < nl * len; e += kLineBlock) {
+      T[i * kTS + t] = x[b0 + e];
+      i += kLineBlock;
+      while (i >= len) {
+        i -= len;
+        ++t;
+      }
+    }
+  } else if (mine) {
+    for (int i = 0; i < len; ++i) T[i * kTS + threadIdx.x] = x[base + (long long)i * stride];
   }
+  __syncthreads();
+  if ((int)threadIdx.x < nl) {
+    // sweeps in chunks of kChunk: the chunk's values and coefficients are read
+    // from LDS into registers before any of the chunk is written back (the
+    // compiler cannot move a read of the shared array above a write to it)
+    double* col = T + threadIdx.x;  // element i at col[i * kTS]
+    double win[P > 0 ? P : 1];
 #pragma unroll
-  for (int k = 0; k < P; ++k) win[k] = 0.0;
-  for (int i = len - 1; i >= 0; --i) {  // backward: L^T z = t
-    const long long o = base + (long long)i * stride;
-    double zv = y[o];
+    for (int k = 0; k < P; ++k) win[k] = 0.0;
+    for (int i0 = 0; i0 < len; i0 += kChunk) {  // forward: L t = alpha x
+      double v[kChunk], cf[kChunk][P + 1];
 #pragma unroll
-    for (int k = 1; k <= P; ++k)
-      if (i + k < len) zv -= L[(long long)(i + k) * W + k] * win[P - k];
-    zv /= L[(long long)i * W];
-    y[o] = zv;
+      for (int c = 0; c < kChunk; ++c) {
+        const int i = i0 + c < len ? i0 + c : len - 1;
+        v[c] = col[i * kTS];
 #pragma unroll
-    for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
-    if (P > 0) win[P - 1] = zv;
+        for (int k = 0; k <= P; ++k) cf[c][k] = Ls[i * W + k];
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (i0 + c < len) {
+          double t = alpha * v[c];
+#pragma unroll
+          for (int k = 1; k <= P; ++k) t -= cf[c][k] * win[P - k];
+          t *= cf[c][0];
+          v[c] = t;
+#pragma unroll
+          for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
+          if (P > 0) win[P - 1] = t;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c)
+        if (i0 + c < len) col[(i0 + c) * kTS] = v[c];
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) win[k] = 0.0;
+    const int nch = (len + kChunk - 1) / kChunk;
+    for (int q = nch - 1; q >= 0; --q) {  // backward: L^T z = t (entries past the end read as 0)
+      const int i0 = q * kChunk;
+      double v[kChunk], d0[kChunk], cf[kChunk][P + 1];  // cf[c][k] = L_{i+k, i} = Ls[(i+k)][k]
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        const int i = i0 + c < len ? i0 + c : len - 1;
+        v[c] = col[i * kTS];
+        d0[c] = Ls[i * W];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) cf[c][k] = i + k < len ? Ls[(i + k) * W + k] : 0.0;
+      }
+#pragma unroll
+      for (int c = kChunk - 1; c >= 0; --c) {
+        if (i0 + c < len) {
+          double zv = v[c];
+#pragma unroll
+          for (int k = 1; k <= P; ++k) zv -= cf[c][k] * win[P - k];
+          zv *= d0[c];
+          v[c] = zv;
+#pragma unroll
+          for (int k = 0; k + 1 < P; ++k) win[k] = win[k + 1];
+          if (P > 0) win[P - 1] = zv;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c)
+        if (i0 + c < len) col[(i0 + c) * kTS] = v[c];
+    }
   }
+  __syncthreads();
+  if (DIR == 0) {
+    const long long b0 = l0 * n1;
+    int t = (int)threadIdx.x / len, i = (int)threadIdx.x % len;
+    for (int e = threadIdx.x; e < nl * len; e += kLineBlock) {
+      y[b0 + e] = T[i * kTS + t];
+      i += kLineBlock;
+      while (i >= len) {
+        i -= len;
+        ++t;
+      }
+    }
+  } else if (mine) {
+    for (int i = 0; i < len; ++i) y[base + (long long)i * stride] = T[i * kTS + threadIdx.x];
+  }
+}
+
+template <int P, int DIR>
+size_t lds_solve_bytes(int len) {
+  return sizeof(double) * ((size_t)((len * (P + 1) + 1) & ~1) + (size_t)len * kTS);
 }
 
 __global__ void k_adi_fill0(double* __restrict__ a, double* __restrict__ b, long long N, const int* __restrict__ flag) {
@@ -170,7 +350,8 @@ std::vector<double> band_of(const std::vector<double>& X, int n, int p) {
   return b;
 }
 
-// Lower band Cholesky of K + w M (both [n][2p+1] bands): [n][p+1], entry (i, i-k).
+// Lower band Cholesky of cK K + w M (both [n][2p+1] bands): [n][p+1], entry (i, i-k),
+// the diagonal stored as its reciprocal.
 bool band_cholesky(const std::vector<double>& K, const std::vector<double>& M, double cK, double w, int n, int p,
                    double* L) {
   const int W = 2 * p + 1, WL = p + 1;
@@ -191,6 +372,7 @@ bool band_cholesky(const std::vector<double>& K, const std::vector<double>& M, d
       l(i, j) = v / ljj;
     }
   }
+  for (int j = 0; j < n; ++j) l(j, j) = 1.0 / l(j, j);  // the solves multiply by the reciprocal
   return true;
 }
 
@@ -220,12 +402,10 @@ double error_norm(const std::vector<double>& w, const std::vector<double>& l1, c
 }
 
 template <int P, int DIR>
-igafd_status line_apply(igafd_ctx* c, const double* A, const double* B, double ca, double cb, const double* x,
-                        const double* x2, double c2, const double* z, double cz, double* y, const int* flag) {
-  const long long lines = DIR == 0 ? (long long)c->n[1] * c->n[2] : DIR == 1 ? (long long)c->n[0] * c->n[2]
-                                                                            : (long long)c->n[0] * c->n[1];
-  hipLaunchKernelGGL((k_line_apply<P, DIR>), dim3((unsigned)((lines + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     c->stream, A, B, ca, cb, x, x2, c2, z, cz, y, c->n[0], c->n[1], c->n[2], flag);
+igafd_status band_apply(igafd_ctx* c, const double* Bd, double ca, const double* x, const double* x2, double c2,
+                        const double* z, double cz, double* y, const int* flag) {
+  hipLaunchKernelGGL((k_band_apply<P, DIR>), dim3((unsigned)((c->N + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+                     Bd, ca, x, x2, c2, z, cz, y, c->n[0], c->n[1], c->n[2], flag);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
@@ -234,10 +414,49 @@ template <int P, int DIR>
 igafd_status line_solve(igafd_ctx* c, const double* L, double alpha, const double* x, double* y, const int* flag) {
   const long long lines = DIR == 0 ? (long long)c->n[1] * c->n[2] : DIR == 1 ? (long long)c->n[0] * c->n[2]
                                                                             : (long long)c->n[0] * c->n[1];
-  hipLaunchKernelGGL((k_line_solve<P, DIR>), dim3((unsigned)((lines + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     c->stream, L, alpha, x, y, c->n[0], c->n[1], c->n[2], flag);
+  const int len = c->n[DIR];
+  const dim3 grid((unsigned)((lines + kLineBlock - 1) / kLineBlock));
+  if (len <= kLdsLineMax) {  // attribute for > 64 KB set at setup (adi_lds_attr)
+    const size_t lds = lds_solve_bytes<P, DIR>(len);
+    hipLaunchKernelGGL((k_line_solve_lds<P, DIR>), grid, dim3(kLineBlock), lds, c->stream, L, alpha, x, y, c->n[0],
+                       c->n[1], c->n[2], len, flag);
+  } else {
+    const size_t lds = sizeof(double) * (size_t)len * (P + 1);
+    if (lds > 64 * 1024) {
+      set_error("ADI line too long for the LDS-staged factor");
+      return IGAFD_ERR_ARG;
+    }
+    hipLaunchKernelGGL((k_line_solve<P, DIR>), grid, dim3(kLineBlock), lds, c->stream, L, alpha, x, y, c->n[0], c->n[1],
+                       c->n[2], len, flag);
+  }
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
+}
+
+// Dynamic LDS above 64 KB needs the kernel attribute; set once per problem at
+// setup (never inside a launch sequence that may be captured).
+template <int P>
+igafd_status lds_attr(const igafd_ctx* c) {
+  const void* fn[3] = {(const void*)&k_line_solve_lds<P, 0>, (const void*)&k_line_solve_lds<P, 1>,
+                       (const void*)&k_line_solve_lds<P, 2>};
+  const size_t need[3] = {lds_solve_bytes<P, 0>(c->n[0]), lds_solve_bytes<P, 1>(c->n[1]), lds_solve_bytes<P, 2>(c->n[2])};
+  for (int d = 0; d < 3; ++d)
+    if (c->n[d] <= kLdsLineMax && need[d] > 64 * 1024)
+      IGAFD_HIP_CHECK(hipFuncSetAttribute(fn[d], hipFuncAttributeMaxDynamicSharedMemorySize, (int)need[d]));
+  return IGAFD_OK;
+}
+
+igafd_status adi_lds_attr(const igafd_ctx* c) {
+  switch (c->p) {
+#define IGAFD_P(P) \
+  case P:          \
+    return lds_attr<P>(c);
+    IGAFD_P(1) IGAFD_P(2) IGAFD_P(3) IGAFD_P(4) IGAFD_P(5) IGAFD_P(6)
+#undef IGAFD_P
+    default:
+      set_error("unsupported degree");
+      return IGAFD_ERR_ARG;
+  }
 }
 
 // s = P_J^-1 r by the steps of Alg. "3D ADI method" (s_0 = v_0 = 0)
@@ -267,17 +486,17 @@ igafd_status apply_p(igafd_ctx* c, const double* r, double* s, double* partial, 
   for (int j = 0; j < J; ++j) {
     const double w = a->omega[j];
     // u_j = (I x M2^-1 K2 x I) s_{j-1}
-    IGAFD_T((line_apply<P, 1>(c, a->bandK[1], nullptr, 1.0, 0.0, s, nullptr, 0.0, nullptr, 0.0, t1, flag)));
+    IGAFD_T((band_apply<P, 1>(c, a->bandK[1], 1.0, s, nullptr, 0.0, nullptr, 0.0, t1, flag)));
     IGAFD_T((line_solve<P, 1>(c, facM(1), 1.0, t1, u, flag)));
     // r*_j = r~ - ((K1 - w M1) x I x I) s_{j-1} - (2 M1 x I x I)(u_j + v_j); s*_j
-    IGAFD_T((line_apply<P, 0>(c, a->bandK[0], a->bandM[0], -1.0, w, s, nullptr, 0.0, rt, 1.0, t1, flag)));
-    IGAFD_T((line_apply<P, 0>(c, nullptr, a->bandM[0], 0.0, -2.0, u, v, 1.0, t1, 1.0, t1, flag)));
+    IGAFD_T((band_apply<P, 0>(c, a->bandKw1 + (size_t)j * n1 * (2 * P + 1), -1.0, s, nullptr, 0.0, rt, 1.0, t1, flag)));
+    IGAFD_T((band_apply<P, 0>(c, a->bandM[0], -2.0, u, v, 1.0, t1, 1.0, t1, flag)));
     IGAFD_T((line_solve<P, 0>(c, facW(0, j), 1.0, t1, t1, flag)));
     // r**_j = (I x M2 x I)(u_j + w s*_j); s**_j
-    IGAFD_T((line_apply<P, 1>(c, nullptr, a->bandM[1], 0.0, 1.0, u, t1, w, nullptr, 0.0, t2, flag)));
+    IGAFD_T((band_apply<P, 1>(c, a->bandM[1], 1.0, u, t1, w, nullptr, 0.0, t2, flag)));
     IGAFD_T((line_solve<P, 1>(c, facW(1, j), 1.0, t2, t2, flag)));
     // b_j = v_j + w s**_j; r_j = (I x I x M3) b_j; s_j; v_{j+1} = b_j - w s_j
-    IGAFD_T((line_apply<P, 2>(c, nullptr, a->bandM[2], 0.0, 1.0, v, t2, w, nullptr, 0.0, t1, flag)));
+    IGAFD_T((band_apply<P, 2>(c, a->bandM[2], 1.0, v, t2, w, nullptr, 0.0, t1, flag)));
     IGAFD_T((line_solve<P, 2>(c, facW(2, j), 1.0, t1, s, flag)));
     hipLaunchKernelGGL(k_adi_vupdate, dim3(vb), dim3(kBlock), 0, c->stream, v, t2, s, w, N, r,
                        j + 1 == J ? partial : nullptr, flag);
@@ -302,6 +521,7 @@ void adi_free(igafd_ctx* c) {
     if (a->bandM[d]) (void)hipFree(a->bandM[d]);
     if (a->fac[d]) (void)hipFree(a->fac[d]);
   }
+  if (a->bandKw1) (void)hipFree(a->bandKw1);
   if (a->work) (void)hipFree(a->work);
   delete a;
   c->adi = nullptr;
@@ -352,6 +572,7 @@ igafd_status adi_setup(igafd_ctx* c, double eps) {
         if (a->bandM[d]) (void)hipFree(a->bandM[d]);
         if (a->fac[d]) (void)hipFree(a->fac[d]);
       }
+      if (a->bandKw1) (void)hipFree(a->bandKw1);
       if (a->work) (void)hipFree(a->work);
     }
   } guard{st.get()};
@@ -372,8 +593,18 @@ igafd_status adi_setup(igafd_ctx* c, double eps) {
     IGAFD_HIP_CHECK(hipMemcpy(st->bandM[d], bM.data(), sizeof(double) * bM.size(), hipMemcpyHostToDevice));
     IGAFD_HIP_CHECK(hipMemcpy(st->fac[d], fac.data(), sizeof(double) * fac.size(), hipMemcpyHostToDevice));
   }
+  {  // K1 - omega_j M1 per parameter, direction 1
+    const int n = c->dir[0].n;
+    const std::vector<double> bK = band_of(c->dir[0].K, n, p), bM = band_of(c->dir[0].M, n, p);
+    std::vector<double> kw((size_t)J * n * W);
+    for (int j = 0; j < J; ++j)
+      for (size_t e = 0; e < bK.size(); ++e) kw[(size_t)j * n * W + e] = bK[e] - w[j] * bM[e];
+    IGAFD_HIP_CHECK(hipMalloc((void**)&st->bandKw1, sizeof(double) * kw.size()));
+    IGAFD_HIP_CHECK(hipMemcpy(st->bandKw1, kw.data(), sizeof(double) * kw.size(), hipMemcpyHostToDevice));
+  }
   IGAFD_HIP_CHECK(hipMalloc((void**)&st->work, sizeof(double) * 5 * (size_t)c->N));
-  (void)W;
+  igafd_status sa = adi_lds_attr(c);
+  if (sa != IGAFD_OK) return sa;
   adi_free(c);
   guard.a = nullptr;
   c->adi = st.release();

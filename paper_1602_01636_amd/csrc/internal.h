@@ -90,6 +90,7 @@ struct igafd_adi {
   double* bandK[3] = {nullptr, nullptr, nullptr};
   double* bandM[3] = {nullptr, nullptr, nullptr};
   double* fac[3] = {nullptr, nullptr, nullptr};
+  double* bandKw1 = nullptr;  // K_1 - omega_j M_1 for every j: [J][n1][2p+1]
   double* work = nullptr;  // rt, v, u, t1, t2: 5 N doubles
 };
 
