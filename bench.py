@@ -22,6 +22,8 @@ Other workloads (--workload), each printing one JSON line of the same form:
            h^-1 = 1024 elements per patch and direction, p = 3: CG + additive Schwarz P_IAS
   adi      thick ring 128^3, p = 3: CG + the three-variable ADI preconditioner P_J (eps = 0.1)
            beside CG + the exact FD apply (the paper's FD-vs-ADI comparison)
+  cube     unit cube, P = A: the FD apply as the direct solver (the paper's Table cube) at
+           h^-1 = 128, 256, 512 (--elements 1024 for the 10^9-unknown case), p = 3 (--degree)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -545,12 +547,110 @@ def run_adi(args, api, torch, synth):
     return out
 
 
+# The paper's Table cube (upper part): FD direct solver on the unit cube,
+# P = A, b = randn, seconds per solve including the 1D eigendecompositions, one
+# core of an i7-5820K (MATLAB); h^-1 -> seconds, per degree
+PAPER_CUBE_FD_S = {
+    1: {128: 0.19, 256: 1.80, 512: 23.02, 1024: 331.01}, 2: {128: 0.15, 256: 1.87, 512: 22.58, 1024: 316.15},
+    3: {128: 0.17, 256: 2.05, 512: 23.45, 1024: 328.65}, 4: {128: 0.17, 256: 1.90, 512: 23.26, 1024: 318.42},
+    5: {128: 0.18, 256: 2.10, 512: 23.65, 1024: 331.06}, 6: {128: 0.17, 256: 1.82, 512: 21.89, 1024: 310.31},
+}
+
+
+def cube_cpu_baseline(E, p):
+    """The oracle's FD apply (FP64, numpy on the host cores) at the same size
+    when it is at most 512^3 elements, else at 512^3 scaled by the FLOPs."""
+    from threadpoolctl import threadpool_info
+
+    import synth
+    from oracle import fd
+    Es = min(E, 512)
+    F = fd.setup(synth.unit_cube(Es, p))
+    n = len(F[0]["lam"])
+    r = np.random.default_rng(1).standard_normal(n ** 3)
+    t0 = time.perf_counter()
+    fd.fd_apply(F, r)
+    t = time.perf_counter() - t0
+    nf = E + p - 2
+    scale = (nf ** 4) / (n ** 4)
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    log(f"cpu baseline: oracle FD apply at {Es}^3 elements: {t:.2f} s on {cores} threads")
+    return {"value": t * scale, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"one oracle FD apply (numpy, FP64) at h^-1={Es}, p={p}" +
+                      (f", scaled by the FLOPs (n^4) to h^-1={E}" if Es != E else "")}
+
+
+def run_cube(args, api, torch, synth):
+    """Unit cube, P = A: the FD apply is the direct solver (the paper's Table
+    cube, right-hand side randn).  Preconditioner-only contexts (no A) at
+    h^-1 = 128, 256, 512 (or --elements); per size the host setup (1D
+    eigendecompositions + upload) and the event-timed applies in FP64, FP32 and
+    BF16.  The timed steps are FP64 direct solves at the largest size."""
+    p = args.degree or 3
+    sizes = [args.elements] if args.elements else [128, 256, 512]
+    gen = torch.Generator(device="cuda")
+    per_size = []
+    for E in sizes:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = api.igafd_setup_precond(synth.unit_cube(E, p))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        gen.manual_seed(E)
+        r = torch.randn(ctx.N, dtype=torch.float64, device="cuda", generator=gen)
+        s = torch.empty_like(r)
+        fl = fd_flops(ctx)
+        reps = 20 if ctx.N < 5e7 else 5
+        t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, r, s), reps)
+                for pr in ("fp64", "fp32", "bf16")}
+        tf = {pr: fl / t / 1e9 for pr, t in t_fd.items()}
+        paper = PAPER_CUBE_FD_S.get(p, {}).get(E)
+        log(f"cube h^-1={E} p={p} n={ctx.n[0]} N={ctx.N}: setup {t_setup:.2f} s; apply " +
+            ", ".join(f"{pr} {t:.2f} ms ({tf[pr]:.1f} TF)" for pr, t in t_fd.items()) +
+            (f"; paper {paper} s" if paper else ""))
+        per_size.append({"elements": E, "n": ctx.n[0], "N": ctx.N, "setup_s": t_setup,
+                         "apply_ms": t_fd, "tflops": tf, "applies_per_s": {pr: 1e3 / t for pr, t in t_fd.items()},
+                         "fp64_mfma_frac": tf["fp64"] / FP64_PEAK_TF,
+                         "solve_s_setup_plus_fp64_apply": t_setup + t_fd["fp64"] / 1e3, "paper_s": paper})
+        if E != sizes[-1]:
+            ctx.close()
+            del r, s
+    for _ in range(args.warmup):
+        api.igafd_apply_precond(ctx, "fp64", r, s)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.igafd_apply_precond(ctx, "fp64", r, s)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if args.copy_calibration:
+        copy_calibration(torch)
+    ms_per_step = 1e3 * float(np.median(times))
+    last = per_size[-1]
+    E = last["elements"]
+    cpu = None if args.no_cpu_baseline else cube_cpu_baseline(E, p)
+    workload = {"workload": f"unit cube, identity map, kappa = 1 (P = A), p={p}, {E}^3 elements, N={ctx.N}, "
+                            f"FD direct solve (one FP64 apply of P^-1 to a randn right-hand side)",
+                "elements": E, "degree": p, "N": ctx.N}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": 0, "sizes": per_size,
+        "roofline": {"bound": "mfma", "achieved": last["tflops"]["fp64"], "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": last["fp64_mfma_frac"], "traffic": None,
+                     "kernel": "k_gemm (six FP64 mode products, tiled MFMA)", "algorithmic_flops": fd_flops(ctx)},
+        "cpu_baseline": cpu})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape", "adi"])
+    ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape", "adi",
+                                                             "cube"])
     ap.add_argument("--elements", type=int, default=0)
     ap.add_argument("--degree", type=int, default=0)
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
@@ -571,7 +671,7 @@ def main():
 
     torch.cuda.set_device(0)
     run = {"ring": run_ring, "warped": run_warped, "batch": run_batch, "learned": run_learned,
-           "square": run_square, "lshape": run_lshape, "adi": run_adi}[args.workload]
+           "square": run_square, "lshape": run_lshape, "adi": run_adi, "cube": run_cube}[args.workload]
     out = run(args, api, torch, synth)
     print(json.dumps(out), flush=True)
 

@@ -101,6 +101,20 @@ typedef struct {
  */
 igafd_status igafd_setup(const igafd_problem* prob, void* stream, igafd_ctx** out);
 
+/*
+ * Preconditioner-only setup: everything igafd_setup builds for P (the
+ * univariate matrices, U_d, D_d, the FD intermediates: 2N doubles), but no A
+ * and no CG workspace.  On the unit square / cube with kappa = 1, P = A
+ * (Sec. 3), so igafd_apply_precond is then the fast-diagonalisation direct
+ * solver of Sec. 4.1 / 5.1 (the paper's Tables square and cube), also at sizes
+ * whose A would not fit (10^9 unknowns take 4 vectors of 8.6 GB, not 1.5 TB
+ * of band).  apply_precond, set_scaling, set_adi, get_adi, load_vector,
+ * spectral_bounds, sizes (band_bytes = 0) and get_eigen work; calls that need
+ * A (apply_A, solve, solve_batched, diagonals, features, scaling_targets,
+ * set_scaling_diag_ratio, autotune) return IGAFD_ERR_ARG.
+ */
+igafd_status igafd_setup_precond(const igafd_problem* prob, void* stream, igafd_ctx** out);
+
 /* Sizes: n[3] dofs per direction (n[2] = 1 in 2D), N = prod n, nnz = stored
  * nonzeros of A counted over the full matrix, band_bytes = device bytes of A. */
 igafd_status igafd_sizes(const igafd_ctx* ctx, int n[3], long long* N, long long* nnz,

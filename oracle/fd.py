@@ -111,6 +111,36 @@ def kron_P(factors):
     return P
 
 
+def apply_P(factors, x):
+    """P x from the Kronecker sum itself, one term per direction, each term a
+    sequence of mode products with the banded 1D matrices (K_j along
+    direction j, M_l along the others; Sec. 2.2 eq. kronprod).  The 1D
+    matrices are used as sparse matrices so that grids of 10^8 points stay
+    within host memory and time."""
+    import scipy.sparse as sps
+
+    shape = tuple(len(f["lam"]) for f in factors[::-1])
+    flat = np.ndim(x) == 1
+    X = np.asarray(x, float).reshape(shape)
+    d = len(factors)
+
+    def along(T, B, direction):
+        ax = _axis(d, direction)
+        T0 = np.moveaxis(T, ax, 0)
+        Y = (B @ T0.reshape(T0.shape[0], -1)).reshape(T0.shape)
+        return np.moveaxis(Y, 0, ax)
+
+    Ms = [sps.csr_matrix(f["M"]) for f in factors]
+    Ks = [sps.csr_matrix(f["K"]) for f in factors]
+    out = np.zeros(shape)
+    for j in range(d):
+        T = X
+        for l in range(d):
+            T = along(T, Ks[l] if l == j else Ms[l], l)
+        out += T
+    return out.reshape(-1) if flat else out
+
+
 def diag_P(factors):
     """Diagonal of P from the 1D diagonals (Sec. 3 Kronecker sum)."""
     d = len(factors)

@@ -75,6 +75,7 @@ _SIGNATURES = {
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
     "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "igafd_setup_precond": (C.c_int, [C.POINTER(igafd_problem), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_lshape_setup": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_set_adi": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "igafd_get_adi": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
@@ -200,6 +201,16 @@ class Context:
 
 def igafd_setup(problem: dict, stream=None) -> Context:
     """Setup of one problem (host 1D setup + device assembly)."""
+    return _setup(problem, stream, "igafd_setup")
+
+
+def igafd_setup_precond(problem: dict, stream=None) -> Context:
+    """Preconditioner-only setup (no A): on the unit square / cube P = A, so
+    igafd_apply_precond is the fast-diagonalisation direct solver."""
+    return _setup(problem, stream, "igafd_setup_precond")
+
+
+def _setup(problem: dict, stream, entry: str) -> Context:
     d = int(problem["dim"])
     pr = igafd_problem()
     pr.dim = d
@@ -221,7 +232,7 @@ def igafd_setup(problem: dict, stream=None) -> Context:
     pr.coef_kind, pr.n_coef_params, pr.coef_params = ck, len(cp), cpa
     pr.quad_per_dir = int(problem.get("quad", 0) or 0)
     h = C.c_void_p()
-    _check(lib().igafd_setup(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
+    _check(getattr(lib(), entry)(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
     n, N, nnz, bb = igafd_sizes(h)
     return Context(h, n, N, nnz, bb, d, pr.degree)
 

@@ -272,6 +272,12 @@ igafd_status create_fd_sub(int p, const Dir1D& d1, const Dir1D& d2, hipStream_t 
   return IGAFD_OK;
 }
 
+bool no_A(const igafd_ctx* c, const char* what) {
+  if (c->band) return false;
+  set_error(std::string(what) + " needs A; this context holds only the preconditioner (igafd_setup_precond)");
+  return true;
+}
+
 bool is_lshape(const igafd_ctx* c, const char* what) {
   if (c->hole < 0) return false;
   set_error(std::string(what) + " is not defined for the L-shaped multi-patch context");
@@ -840,8 +846,9 @@ using namespace igafd;
 namespace igafd {
 namespace {
 // fd = false: no univariate eigendecompositions (a context whose
-// preconditioner is applied by other contexts)
-igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, bool fd) {
+// preconditioner is applied by other contexts); with_A = false: no A and no
+// CG workspace (a context that only applies P^-1)
+igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, bool fd, bool with_A = true) {
   if (!pr || !out) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
@@ -879,6 +886,16 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
   if (c->fd_tiles < 1 || c->fd_tiles > 8) c->fd_tiles = 2;
   if (const char* e = std::getenv("IGAFD_FD_FUSED")) c->fd_fused = std::atoi(e) != 0;
   if (const char* e = std::getenv("IGAFD_FD_GEMM")) c->fd_gemm = std::atoi(e) != 0;
+  if (!with_A) {
+    // FD intermediates (FP64 is the widest) and the block partials of the
+    // preconditioner's (r, s) product and of the spectral bounds
+    for (int b = 0; b < 2; ++b) IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[b], sizeof(double) * (size_t)c->N));
+    c->npartial = std::max(1025, fd_dot_blocks_max(c.get()));
+    IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
+    IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+    *out = c.release();
+    return IGAFD_OK;
+  }
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->band, sizeof(double) * (size_t)c->H * (size_t)c->Ns));
   if ((s = alloc_workspace(c.get())) != IGAFD_OK) return s;
   {
@@ -949,6 +966,10 @@ void igafd_destroy(igafd_ctx* c) {
 
 igafd_status igafd_setup(const igafd_problem* pr, void* stream, igafd_ctx** out) {
   return setup_impl(pr, stream, out, true);
+}
+
+igafd_status igafd_setup_precond(const igafd_problem* pr, void* stream, igafd_ctx** out) {
+  return setup_impl(pr, stream, out, true, false);
 }
 
 igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, void* stream, igafd_ctx** out) {
@@ -1063,7 +1084,7 @@ igafd_status igafd_sizes(const igafd_ctx* c, int n[3], long long* N, long long* 
     for (int l = 0; l < 3; ++l) n[l] = c->n[l];
   if (N) *N = c->N;
   if (nnz) *nnz = c->nnz;
-  if (band_bytes) *band_bytes = (long long)sizeof(double) * c->H * c->Ns;
+  if (band_bytes) *band_bytes = c->band ? (long long)sizeof(double) * c->H * c->Ns : 0;
   return IGAFD_OK;
 }
 
@@ -1081,6 +1102,7 @@ igafd_status igafd_apply_A(igafd_ctx* c, const double* x, double* y) {
     set_error("apply_A needs distinct non-null vectors");
     return IGAFD_ERR_ARG;
   }
+  if (no_A(c, "igafd_apply_A")) return IGAFD_ERR_ARG;
   return spmv_unpadded(c, x, y, nullptr, nullptr);
 }
 
@@ -1114,6 +1136,7 @@ igafd_status igafd_diagonals(igafd_ctx* c, double* dA, double* dP) {
     return IGAFD_ERR_ARG;
   }
   if (is_lshape(c, "igafd_diagonals")) return IGAFD_ERR_ARG;
+  if (no_A(c, "igafd_diagonals")) return IGAFD_ERR_ARG;
   return diagonals(c, dA, dP);
 }
 
@@ -1123,6 +1146,7 @@ igafd_status igafd_features(igafd_ctx* c, float* feat) {
     return IGAFD_ERR_ARG;
   }
   if (is_lshape(c, "igafd_features")) return IGAFD_ERR_ARG;
+  if (no_A(c, "igafd_features")) return IGAFD_ERR_ARG;
   return features(c, feat);
 }
 
@@ -1132,6 +1156,7 @@ igafd_status igafd_scaling_targets(igafd_ctx* c, float* t) {
     return IGAFD_ERR_ARG;
   }
   if (is_lshape(c, "igafd_scaling_targets")) return IGAFD_ERR_ARG;
+  if (no_A(c, "igafd_scaling_targets")) return IGAFD_ERR_ARG;
   return scaling_targets(c, t);
 }
 
@@ -1141,6 +1166,7 @@ igafd_status igafd_set_scaling_diag_ratio(igafd_ctx* c) {
     return IGAFD_ERR_ARG;
   }
   if (is_lshape(c, "the scaled preconditioner")) return IGAFD_ERR_ARG;
+  if (no_A(c, "igafd_set_scaling_diag_ratio")) return IGAFD_ERR_ARG;
   if (!c->scaling) IGAFD_HIP_CHECK(hipMalloc((void**)&c->scaling, sizeof(double) * c->N));
   igafd_status st = diag_ratio_scaling(c, c->scaling);
   if (st == IGAFD_OK) c->scaling_set = true;
@@ -1170,6 +1196,7 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
   }
   for (int i = 0; i < count; ++i) {
     if (ctxs[i] && is_lshape(ctxs[i], "igafd_solve_batched")) return IGAFD_ERR_ARG;
+    if (ctxs[i] && no_A(ctxs[i], "igafd_solve_batched")) return IGAFD_ERR_ARG;
     if (ctxs[i] && ctxs[i]->adi) {
       set_error("igafd_solve_batched runs the FD preconditioner only");
       return IGAFD_ERR_ARG;
@@ -1213,11 +1240,13 @@ igafd_status igafd_autotune(igafd_ctx* c, int fd_tiles, int spmv_rows) {
     }
     if (fd_tiles > 0) c->fd_tiles = fd_tiles;
     if (spmv_rows > 0) {
+      if (no_A(c, "the A-product shape")) return IGAFD_ERR_ARG;
       c->spmv_rows = spmv_rows;
       return spmv_set_tile(c, 0, 0);  // an explicit row count selects the row-parallel kernel
     }
     return IGAFD_OK;
   }
+  if (no_A(c, "igafd_autotune")) return IGAFD_ERR_ARG;
   return autotune_impl(c, 3);
 }
 
@@ -1226,6 +1255,7 @@ igafd_status igafd_solve(igafd_ctx* c, const double* b, double* u, const igafd_s
     set_error("solve needs a context, distinct b and u, and options");
     return IGAFD_ERR_ARG;
   }
+  if (no_A(c, "igafd_solve")) return IGAFD_ERR_ARG;
   return solve_impl(c, b, u, o, info);
 }
 

@@ -694,12 +694,14 @@ int dot_blocks_for(const igafd_ctx* c) {
   return grid_x(C, 1, ms.nblk);
 }
 
-// 2D applies of long directions use the tiled products of gemm.hip (FP64 and
-// FP32; IGAFD_FD_GEMM=0/1 at setup forces the choice)
+// Applies with long directions use the tiled products of gemm.hip (FP64 and
+// FP32): 2D grids with n1 + n2 >= 384, 3D tensors with a direction longer
+// than the fused passes take.  IGAFD_FD_GEMM=0/1 at setup forces the choice.
 constexpr int kGemmAutoN = 384;
 bool use_gemm(const igafd_ctx* c, int prec) {
-  if (c->dim != 2 || prec == IGAFD_BF16) return false;
+  if (prec == IGAFD_BF16) return false;
   if (c->fd_gemm >= 0) return c->fd_gemm != 0;
+  if (c->dim == 3) return !fused_ok(c);
   return c->n[0] + c->n[1] >= kGemmAutoN;
 }
 
@@ -742,6 +744,10 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
   if ((stt = (x)) != IGAFD_OK) \
     return stt;
   if (c->dim == 3) {
+    if constexpr (!std::is_same<Pr, PBF16>::value) {
+      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : IGAFD_FP32;
+      if (use_gemm(c, prec)) return fd_apply_gemm3d(c, prec, r, s, S, partial, flag);
+    }
     // forward: direction 1 (fast axis), 2, 3 (+ eigenvalue scaling)
     IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2 * n3, 1, 0, e_in)));
     IGAFD_TRY((launch_mode<Pr, false, T, T>(st, c->fd_tiles, b0, b1, wmat<Pr>(d[1], 0), d[1].npad, n2, n1, n3,
@@ -856,7 +862,7 @@ igafd_status schwarz_apply(igafd_ctx* c, int prec, const double* r, double* s, c
 
 }  // namespace
 
-bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c); }
+bool fd_fused_ok(const igafd_ctx* c) { return fused_ok(c) && !use_gemm(c, IGAFD_FP64); }
 
 int fd_dot_blocks(const igafd_ctx* c, int prec) {
   if (c->adi) return (int)((c->N + kBlock - 1) / kBlock);
@@ -868,7 +874,7 @@ int fd_dot_blocks(const igafd_ctx* c, int prec) {
 int fd_dot_blocks_max(const igafd_ctx* c) {
   const int C = (c->dim == 3) ? c->n[1] * c->n[2] : c->n[1];
   int m = std::max(slice_blocks(c), schwarz_blocks(c));
-  if (c->dim == 2) m = std::max(m, fd_gemm_blocks(c));
+  m = std::max(m, fd_gemm_blocks(c));
   for (int t = 1; t <= 8; ++t) {
     const int g = grid_x(C, 1, mode_shape(c->n[0], t).nblk);
     if (g > m) m = g;
@@ -880,7 +886,7 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
                       const int* flag) {
   if (c->adi) return adi_apply(c, prec, r, s, S, partial, flag);
   if (c->hole >= 0) return schwarz_apply(c, prec, r, s, S, partial, flag);
-  if (c->fd_fused && fused_ok(c)) {
+  if (c->fd_fused && fused_ok(c) && !use_gemm(c, prec)) {
     const DevDir* d = c->ddir;
     switch (prec) {
       case IGAFD_FP64: {

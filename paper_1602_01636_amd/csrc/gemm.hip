@@ -64,6 +64,8 @@ constexpr int kPad = 16;
 struct GEpi {
   const double* lrow = nullptr;  // with lcol: C[m][n] /= lrow[m] + lcol[n]
   const double* lcol = nullptr;
+  const double* lcol2 = nullptr; // 3D: C[m][n] /= lrow[m] + lcol[n % n1] + lcol2[n / n1]
+  int n1 = 1;
   const double* Sa = nullptr;    // A[m][k] *= Sa[m * lda + k] (PRE)
   const double* Sc = nullptr;    // C[m][n] *= Sc[m * ldc + n]
   const double* rdot = nullptr;  // with partial: block sums of rdot[m * ldc + n] * C[m][n]
@@ -83,6 +85,13 @@ struct GProb {
   TC* C;
   long long ldc;
   int M, N, K, tiles_n, ntiles;
+  // batch of products sharing A: B and C of product b start b * sb, b * sc
+  // further (the epilogue arrays index like C)
+  int batch, tiles_b;
+  long long sb, sc;
+  // tile order: false = along N first (blocks of a run share an A row panel),
+  // true = along M first (they share a B column panel; for M << N)
+  bool mfast;
   GEpi ep;
 };
 
@@ -127,6 +136,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA,
   const long long lda = second ? p1.lda : p0.lda, ldb = second ? p1.ldb : p0.ldb, ldc = second ? p1.ldc : p0.ldc;
   const int M = second ? p1.M : p0.M, N = second ? p1.N : p0.N, K = second ? p1.K : p0.K;
   const int tiles_n = second ? p1.tiles_n : p0.tiles_n, ntiles = second ? p1.ntiles : p0.ntiles;
+  const int tiles_b = second ? p1.tiles_b : p0.tiles_b;
+  const bool mfast = second ? p1.mfast : p0.mfast;
+  const long long sb = second ? p1.sb : p0.sb, sc = second ? p1.sc : p0.sc;
   const GEpi ep = second ? p1.ep : p0.ep;
   using V = typename G::V;
   using acc_t = typename G::acc;
@@ -145,7 +157,11 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA,
     if (ep.partial && threadIdx.x == 0) ep.partial[bid] = 0.0;
     return;
   }
-  const int tm0 = (tile / tiles_n) * BM, tn0 = (tile % tiles_n) * BN;
+  const int bt = tile / tiles_b, tl = tile - bt * tiles_b;
+  const int tiles_m = tiles_b / tiles_n;
+  const int tm0 = (mfast ? tl % tiles_m : tl / tiles_n) * BM, tn0 = (mfast ? tl / tiles_m : tl % tiles_n) * BN;
+  B += bt * sb;
+  const long long cb = bt * sc;  // offset of this product's C (and epilogue arrays)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int wm0 = (wave >> 1) * TM * 16, wn0 = (wave & 1) * TN * 16;
@@ -269,8 +285,8 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA,
         const int n = tn0 + wn0 + j * 16 + col;
         if (m < M && n < N) {
           double v = (double)acc[i][j][r];
-          const long long c = (long long)m * ldc + n;
-          if (ep.lrow) v /= ep.lrow[m] + ep.lcol[n];
+          const long long c = cb + (long long)m * ldc + n;
+          if (ep.lrow) v /= ep.lcol2 ? ep.lrow[m] + ep.lcol[n % ep.n1] + ep.lcol2[n / ep.n1] : ep.lrow[m] + ep.lcol[n];
           if (ep.Sc) v *= ep.Sc[c];
           C[c] = (TC)v;
           if (ep.partial) dot += ep.rdot[c] * v;
@@ -304,7 +320,7 @@ int device_cus() {
 // so the number of blocks of the last product (which carry the (r, s)
 // partials) is known from the shape alone.  IGAFD_GEMM_TILE=<tm>x<tn>
 // overrides it (tuning).
-Cfg pick(int M, int N, int M1 = 0, int N1 = 0) {
+Cfg pick(int M, int N, int M1 = 0, int N1 = 0, int batch = 1) {
   if (const char* e = std::getenv("IGAFD_GEMM_TILE")) {
     const int tm = std::atoi(e), tn = std::strchr(e, 'x') ? std::atoi(std::strchr(e, 'x') + 1) : 0;
     if ((tm == 2 || tm == 4) && (tn == 2 || tn == 4) && !(tm == 4 && tn == 4)) return {tm, tn};
@@ -316,7 +332,7 @@ Cfg pick(int M, int N, int M1 = 0, int N1 = 0) {
   for (const Cfg& g : cand) {
     const size_t lds = sizeof(double) * 2 * kBK * ((2 * g.tm * 16 + kPad) + (2 * g.tn * 16 + kPad));
     if (lds > 64 * 1024) continue;
-    long long tiles = (long long)((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
+    long long tiles = (long long)batch * ((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
     if (M1 > 0) tiles += (long long)((M1 + 32 * g.tm - 1) / (32 * g.tm)) * ((N1 + 32 * g.tn - 1) / (32 * g.tn));
     const long long cost = (tiles + cus - 1) / cus * (32LL * g.tm) * (32LL * g.tn);
     if (best_cost < 0 || cost < best_cost) {  // candidates run from large to small tiles
@@ -327,25 +343,35 @@ Cfg pick(int M, int N, int M1 = 0, int N1 = 0) {
   return best;
 }
 
-int grid_of(int M, int N, Cfg g) {
-  const int tiles = ((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
-  return 8 * ((tiles + 7) / 8);
+int grid_of(int M, int N, Cfg g, int batch = 1) {
+  const long long tiles = (long long)batch * ((M + 32 * g.tm - 1) / (32 * g.tm)) * ((N + 32 * g.tn - 1) / (32 * g.tn));
+  return (int)(8 * ((tiles + 7) / 8));
 }
 
 // Launch one product, or two sharing a launch (q1 == nullptr: one).
 template <class G, bool BT, typename TA, typename TB, typename TC>
 igafd_status launch(hipStream_t st, GProb<TA, TB, TC> q0, const GProb<TA, TB, TC>* q1) {
   using V = typename G::V;
-  const Cfg g = q1 ? pick(q0.M, q0.N, q1->M, q1->N) : pick(q0.M, q0.N);
+  if (q1 && (q0.batch != 1 || q1->batch != 1)) {
+    set_error("internal: paired products are not batched");
+    return IGAFD_ERR_ARG;
+  }
+  const Cfg g = q1 ? pick(q0.M, q0.N, q1->M, q1->N) : pick(q0.M, q0.N, 0, 0, q0.batch);
   auto shape = [&](GProb<TA, TB, TC>& q) {
     q.tiles_n = (q.N + 32 * g.tn - 1) / (32 * g.tn);
-    q.ntiles = ((q.M + 32 * g.tm - 1) / (32 * g.tm)) * q.tiles_n;
+    q.tiles_b = ((q.M + 32 * g.tm - 1) / (32 * g.tm)) * q.tiles_n;
+    q.ntiles = q.tiles_b * q.batch;
   };
   shape(q0);
   GProb<TA, TB, TC> p1 = q1 ? *q1 : q0;
   shape(p1);
-  const int grid0 = grid_of(q0.M, q0.N, g);
-  const dim3 grid((unsigned)(grid0 + (q1 ? grid_of(p1.M, p1.N, g) : 0)));
+  const long long grid_all = (long long)grid_of(q0.M, q0.N, g, q0.batch) + (q1 ? grid_of(p1.M, p1.N, g) : 0);
+  if ((long long)q0.tiles_b * q0.batch >= (1LL << 31) || grid_all >= (1LL << 31)) {
+    set_error("product too large for one launch");
+    return IGAFD_ERR_ARG;
+  }
+  const int grid0 = grid_of(q0.M, q0.N, g, q0.batch);
+  const dim3 grid((unsigned)grid_all);
 #define IGAFD_G(TM, TN)                                                                                         \
   if (g.tm == TM && g.tn == TN) {                                                                               \
     constexpr size_t lds = lds_bytes<TM, TN, V>();                                                              \
@@ -375,6 +401,9 @@ GProb<TA, TB, TC> prob(const TA* A, long long lda, const TB* B, long long ldb, T
   q.M = M;
   q.N = N;
   q.K = K;
+  q.batch = 1;
+  q.sb = q.sc = 0;
+  q.mfast = false;
   q.ep = ep;
   return q;
 }
@@ -444,9 +473,91 @@ igafd_status apply2d(const Job* jobs, int count, const double* S, double* partia
   return launch<G, true>(st, a4[0], two ? &a4[1] : nullptr);
 }
 
+// One 3D FD apply (Sec. 5.1 Alg. 3, transposes as in the 2D algorithm) by six
+// products on the (n3, n2, n1) tensor:
+//   direction 1: C (n2 n3 x n1) = X (n2 n3 x n1) Wm^T      (the fast axis)
+//   direction 2: C_i3 (n2 x n1) = Wm X_i3 (n2 x n1)         (n3 products, one launch)
+//   direction 3: C (n3 x n1 n2) = Wm X (n3 x n1 n2)         (tiles along M first)
+// with the division by lam1 + lam2 + lam3 in the epilogue of the forward
+// direction-3 product, S on the first input and the last output, and the
+// (r, s) partials in the last epilogue.
+template <class G, typename T>
+igafd_status apply3d(igafd_ctx* c, const double* r, double* s, const double* S, double* partial, const int* flag) {
+  using V = typename G::V;
+  const DevDir* d = c->ddir;
+  const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+  const long long plane = (long long)n1 * n2;
+  if ((long long)n2 * n3 >= (1LL << 31) || plane >= (1LL << 31)) {
+    set_error("grid too large for the tiled products");
+    return IGAFD_ERR_ARG;
+  }
+  T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
+  T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
+  GEpi e0, e_in, e_lam, e_out;
+  e0.flag = e_in.flag = e_lam.flag = e_out.flag = flag;
+  e_in.Sa = S;
+  e_lam.lrow = d[2].lam;
+  e_lam.lcol = d[0].lam;
+  e_lam.lcol2 = d[1].lam;
+  e_lam.n1 = n1;
+  e_out.Sc = S;
+  if (partial) {
+    if (fd_gemm_blocks(c) > c->npartial) {
+      set_error("internal: FD grid larger than the partial-sum buffer");
+      return IGAFD_ERR_ARG;
+    }
+    e_out.rdot = r;
+    e_out.partial = partial;
+  }
+  auto dir1 = [&](const auto* X, auto* Y, int which, const GEpi& ep) {
+    return prob(X, n1, wm<G>(d[0], which), d[0].npad, Y, n1, n2 * n3, n1, n1, ep);
+  };
+  auto dir2 = [&](const T* X, T* Y, int which) {
+    auto q = prob(wm<G>(d[1], which), d[1].npad, X, n1, Y, n1, n2, n1, n2, e0);
+    q.batch = n3;
+    q.sb = q.sc = plane;
+    return q;
+  };
+  auto dir3 = [&](const T* X, T* Y, int which, const GEpi& ep) {
+    auto q = prob(wm<G>(d[2], which), d[2].npad, X, plane, Y, plane, n3, (int)plane, n3, ep);
+    q.mfast = true;
+    return q;
+  };
+  const hipStream_t st = c->stream;
+  igafd_status stt;
+  if ((stt = launch<G, true>(st, dir1(r, b0, 0, e_in), (const GProb<double, V, T>*)nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, dir2(b0, b1, 0), (const GProb<V, T, T>*)nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, dir3(b1, b0, 0, e_lam), (const GProb<V, T, T>*)nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, dir3(b0, b1, 1, e0), (const GProb<V, T, T>*)nullptr)) != IGAFD_OK) return stt;
+  if ((stt = launch<G, false>(st, dir2(b1, b0, 1), (const GProb<V, T, T>*)nullptr)) != IGAFD_OK) return stt;
+  return launch<G, true>(st, dir1((const T*)b0, s, 1, e_out), (const GProb<T, V, double>*)nullptr);
+}
+
 }  // namespace
 
-int fd_gemm_blocks(const igafd_ctx* c) { return grid_of(c->n[1], c->n[0], pick(c->n[1], c->n[0])); }
+// blocks of the last product (one partial each): 2D S = Z U1^T has n2 rows,
+// 3D the direction-1 product has n2 n3
+int fd_gemm_blocks(const igafd_ctx* c) {
+  const int rows = (int)(c->N / c->n[0]);
+  return grid_of(rows, c->n[0], pick(rows, c->n[0]));
+}
+
+igafd_status fd_apply_gemm3d(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
+                             const int* flag) {
+  if (c->dim != 3) {
+    set_error("internal: 3D tiled products need a 3D context");
+    return IGAFD_ERR_ARG;
+  }
+  switch (prec) {
+    case IGAFD_FP64:
+      return apply3d<G64, double>(c, r, s, S, partial, flag);
+    case IGAFD_FP32:
+      return apply3d<G32, float>(c, r, s, S, partial, flag);
+    default:
+      set_error("internal: tiled products run in FP64 or FP32");
+      return IGAFD_ERR_ARG;
+  }
+}
 
 igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* S, double* partial,
                              const int* flag, int ldr, int lds) {

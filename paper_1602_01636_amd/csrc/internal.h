@@ -167,6 +167,8 @@ bool fd_fused_ok(const igafd_ctx* c);
 // sub-blocks of wider grids (row strides ldr, lds; 0 = n1)
 igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                              double* partial_rz, const int* flag, int ldr, int lds);
+igafd_status fd_apply_gemm3d(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
+                             double* partial, const int* flag);
 int fd_gemm_blocks(const igafd_ctx* c);  // blocks (= (r, s) partials) of the last product
 // adi.hip
 igafd_status adi_setup(igafd_ctx* c, double eps);

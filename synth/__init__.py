@@ -122,6 +122,12 @@ def square_2d(E: int = 64, p: int = 3) -> dict:
     return uniform_problem(2, E, p)
 
 
+def unit_cube(E: int = 512, p: int = 3) -> dict:
+    """3D unit cube, identity map, K = I: P = A, so the FD apply is the direct
+    solver (the paper's Table cube, h^-1 = E, right-hand side randn)."""
+    return uniform_problem(3, E, p)
+
+
 def thick_ring(E: int = 128, p: int = 3) -> dict:
     """3D thick quarter ring, K = I."""
     return uniform_problem(3, E, p, geometry={"kind": "ring"})

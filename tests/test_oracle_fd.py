@@ -79,3 +79,20 @@ def test_fd_scaling_is_symmetric_positive(rng):
     r = rng.standard_normal(P.shape[0])
     ref = S * np.linalg.solve(P, S * r)
     np.testing.assert_allclose(fd.fd_apply(F, r, scaling=S), ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 1), (3, 3)])
+def test_apply_P_matches_kron_and_assembly(dim, p, rng):
+    # banded Kronecker-sum product == the explicit Kronecker matrix, and on the
+    # unit square / cube with kappa = 1 (P = A, Sec. 3) == the assembled A
+    prob = _problem(dim, p, seed=40 + dim + p)
+    F = fd.setup(prob)
+    x = rng.standard_normal(int(np.prod([len(f["lam"]) for f in F])))
+    y = fd.apply_P(F, x)
+    np.testing.assert_allclose(y, fd.kron_P(F) @ x, rtol=0, atol=1e-12 * np.abs(y).max())
+    from oracle import assembly
+    A = assembly.assemble_matrix(prob)
+    np.testing.assert_allclose(y, A @ x, rtol=0, atol=1e-11 * np.abs(y).max())
+    # FD is its inverse
+    r = rng.standard_normal(x.size)
+    np.testing.assert_allclose(fd.apply_P(F, fd.fd_apply(F, r)), r, rtol=0, atol=1e-9 * np.abs(r).max())
