@@ -323,7 +323,7 @@ int device_cus() {
 Cfg pick(int M, int N, int M1 = 0, int N1 = 0, int batch = 1) {
   if (const char* e = std::getenv("IGAFD_GEMM_TILE")) {
     const int tm = std::atoi(e), tn = std::strchr(e, 'x') ? std::atoi(std::strchr(e, 'x') + 1) : 0;
-    if ((tm == 2 || tm == 4) && (tn == 2 || tn == 4) && !(tm == 4 && tn == 4)) return {tm, tn};
+    if ((tm == 2 || tm == 4) && (tn == 2 || tn == 4)) return {tm, tn};
   }
   const Cfg cand[4] = {{4, 4}, {4, 2}, {2, 4}, {2, 2}};
   const long long cus = device_cus();
@@ -341,6 +341,13 @@ Cfg pick(int M, int N, int M1 = 0, int N1 = 0, int batch = 1) {
     }
   }
   return best;
+}
+
+// blocks whose LDS exceeds the default 64 KB need the attribute raised once
+template <typename K>
+hipError_t lds_attr(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 int grid_of(int M, int N, Cfg g, int batch = 1) {
@@ -375,6 +382,12 @@ igafd_status launch(hipStream_t st, GProb<TA, TB, TC> q0, const GProb<TA, TB, TC
 #define IGAFD_G(TM, TN)                                                                                         \
   if (g.tm == TM && g.tn == TN) {                                                                               \
     constexpr size_t lds = lds_bytes<TM, TN, V>();                                                              \
+    if (lds > 64 * 1024) {                                                                                      \
+      static const hipError_t e0 = lds_attr(k_gemm<G, TM, TN, BT, false, TA, TB, TC>, lds);                    \
+      static const hipError_t e1 = lds_attr(k_gemm<G, TM, TN, BT, true, TA, TB, TC>, lds);                     \
+      IGAFD_HIP_CHECK(e0);                                                                                      \
+      IGAFD_HIP_CHECK(e1);                                                                                      \
+    }                                                                                                           \
     if (q0.ep.Sa || p1.ep.Sa)                                                                                   \
       hipLaunchKernelGGL((k_gemm<G, TM, TN, BT, true, TA, TB, TC>), grid, dim3(kBlock), lds, st, q0, p1, grid0); \
     else                                                                                                        \
