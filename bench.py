@@ -151,6 +151,29 @@ def timed_solves(api, torch, ctx, b, u, steps, warmup, **kw):
     return times, infos
 
 
+def oracle_fd_apply_times(prob, reps=3):
+    """The oracle's FD apply (numpy mode products, FP64) at the full size, on
+    one host thread (as the paper's single core) and on all of them: best of
+    `reps` per thread count."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import fd
+    F = fd.setup(prob)
+    n = [len(f["lam"]) for f in F]
+    r = np.random.default_rng(2).standard_normal(int(np.prod(n)))
+    out = {}
+    for label, limit in (("1_thread", 1), ("all_threads", None)):
+        with threadpool_limits(limits=limit):
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+            best = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fd.fd_apply(F, r)
+                best = min(best, time.perf_counter() - t0)
+        out[label] = {"s": best, "threads": int(threads)}
+    return out
+
+
 def cpu_baseline(target_iters, n_full, p, nnz_full):
     """The FP64 oracle (NumPy/SciPy, as it stands) on a bounded sample of the
     same workload: the thick ring at 32^3 elements, p = 3.  Its time per CG
@@ -183,8 +206,9 @@ def cpu_baseline(target_iters, n_full, p, nnz_full):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    fd_apply = oracle_fd_apply_times(synth.thick_ring(E=n_full - p + 2, p=p))
     return {"value": per_iter * flops_f / flops_s * target_iters, "unit": "s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "fd_apply_s": fd_apply,
             "sample": f"oracle PCG on the thick ring at {E}^3 elements p={p} (N={N_s}), {reps} solves, "
                       f"{per_iter * 1e3:.2f} ms/iteration, scaled by FLOPs/iteration to {n_full}^3 dofs "
                       f"and x {target_iters} iterations",
@@ -212,6 +236,17 @@ def rhs(api, torch, synth, ctx):
     b = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
     api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
     return b
+
+
+# The paper's Table thick_ring (CG + P): iterations and seconds on one core of
+# an i7-5820K (MATLAB R2015a, FP64 implied), setup included; its map, right-hand
+# side and tolerance are not stated, so this is context, not a like-for-like figure
+PAPER_RING = {
+    (128, 2): {"iters": 28, "s": 14.14}, (128, 3): {"iters": 28, "s": 32.01}, (128, 4): {"iters": 28, "s": 61.22},
+    (64, 3): {"iters": 27, "s": 3.35}, (32, 3): {"iters": 26, "s": 0.38},
+}
+for _v in PAPER_RING.values():
+    _v.update(hardware="one core of an i7-5820K, MATLAB R2015a", source="Table thick_ring (CG + P)")
 
 
 def run_ring(args, api, torch, synth):
@@ -256,7 +291,8 @@ def run_ring(args, api, torch, synth):
         "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
         "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
         "variants": variants, "setup_s": t_setup, "wall_s_timed": wall,
-        "spectral_bounds": [qlo, qhi], "kappa_bound": qhi / qlo,
+        "solve_ms": {"median": 1e3 * float(np.median(times)), "min": 1e3 * min(times), "max": 1e3 * max(times)},
+        "spectral_bounds": [qlo, qhi], "kappa_bound": qhi / qlo, "paper": PAPER_RING.get((E, p)),
         "roofline": roofline(kr, f"thick_ring E={E} p={p}"), "fd_roofline": fd_roofline(kr),
         "cpu_baseline": cpu})
     ctx.close()
