@@ -16,6 +16,10 @@ Readings (the paper cites Douglas for the parameters without restating them):
     eigenvalues (the bound of the paper's rho_J over [a, b]^3 restricted to
     the spectrum).
   * eps = 0.1, the tolerance of the paper's 3D experiments.
+  * Greedy parameters (eq. greedy1/2), the paper's alternative: the triple
+    of largest remaining error over the actual eigenvalue triples (as for
+    rho_J), the minimiser of |g| there in closed form (best_parameter), and
+    sqrt(a b) as the first parameter, which the paper leaves open.
 """
 from __future__ import annotations
 
@@ -64,6 +68,50 @@ def parameters(factors, eps=0.1):
         if r <= eps:
             return w, r, J0
     return w, r, J0
+
+
+def best_parameter(l1, l2, l3):
+    """eq. greedy2: the omega >= 0 that minimises |g(omega; l1, l2, l3)|,
+    g = 1 - 2 omega^2 S / ((omega + l1)(omega + l2)(omega + l3)).
+
+    g = 0 where (omega + l1)(omega + l2)(omega + l3) = 2 S omega^2, i.e. at the
+    positive roots of omega^3 - S omega^2 + e2 omega + e3 (none or two, by the
+    signs of the coefficients); the smaller one is taken.  Without such a root
+    g > 0 everywhere and the minimum is where 2 S omega^2 / prod(omega + l_d)
+    peaks: d/d omega log(...) = 2/omega - sum 1/(omega + l_d) = 0, i.e. the one
+    positive root of omega^3 - e2 omega - 2 e3.  (S, e2, e3: the elementary
+    symmetric functions of l1, l2, l3.)"""
+    S = l1 + l2 + l3
+    e2 = l1 * l2 + l1 * l3 + l2 * l3
+    e3 = l1 * l2 * l3
+
+    def positive_roots(coef):
+        r = np.roots(coef)
+        return sorted(float(x.real) for x in r if abs(x.imag) <= 1e-9 * abs(x) and x.real > 0)
+
+    zeros = positive_roots([1.0, -S, e2, e3])
+    if zeros:
+        return zeros[0]
+    return positive_roots([1.0, 0.0, -e2, -2.0 * e3])[-1]
+
+
+def greedy_parameters(factors, eps=0.1):
+    """(omegas, rho_J, J0) by the greedy rule of eq. greedy1/2: after k steps
+    take the eigenvalue triple where |prod_{j<=k} g_j| is largest (the first
+    one in (k3, k2, k1) order on ties) and the next omega by best_parameter;
+    stop once the largest |prod g_j| is <= eps, or at J0 steps.  The first
+    parameter is sqrt(a b), the one-parameter choice of the geometric rule."""
+    a, b = spectrum_interval(factors)
+    J0 = max(1, math.ceil(1.16 * math.log(b / a) * math.log(1.0 / eps)))
+    l1, l2, l3 = (f["lam"] for f in factors)
+    L1, L2, L3 = l1[None, None, :], l2[None, :, None], l3[:, None, None]
+    w = [math.sqrt(a * b)]
+    G = error_factor(w, L1, L2, L3)
+    while np.abs(G).max() > eps and len(w) < J0:
+        k3, k2, k1 = np.unravel_index(np.argmax(np.abs(G)), G.shape)
+        w.append(best_parameter(float(l1[k1]), float(l2[k2]), float(l3[k3])))
+        G = G * error_factor(w[-1:], L1, L2, L3)
+    return np.array(w), float(np.abs(G).max()), J0
 
 
 def _along(X, B, direction):

@@ -103,3 +103,49 @@ def test_parameter_rule(name, prob):
     assert np.all(np.diff(w) > 0) and abs(w[0] - a) <= 1e-12 * a and abs(w[-1] - b) <= 1e-12 * b
     if len(w) > 1:   # the count is the smallest that meets the tolerance
         assert adi.rho(adi.geometric_parameters(a, b, len(w) - 1), [f["lam"] for f in F]) > eps
+
+
+def test_best_parameter_minimises_g():
+    """eq. greedy2 in closed form against a brute-force scan over omega."""
+    rng = np.random.default_rng(11)
+    grid = np.exp(np.linspace(np.log(1e-3), np.log(1e6), 400001))
+    for _ in range(12):
+        l = rng.uniform(0.5, 2000.0, 3) if _ % 2 else np.exp(rng.uniform(0.0, 9.0, 3))
+        w = adi.best_parameter(*l)
+        g = lambda om: np.abs(adi.error_factor([om], l[0], l[1], l[2]))
+        scan = np.min(np.abs(1.0 - 2.0 * grid ** 2 * l.sum() / np.prod(grid[:, None] + l[None, :], axis=1)))
+        assert float(g(w)) <= scan + 1e-9
+        # and, where g has zeros, the smaller zero: no omega below w reaches g = 0
+        if float(g(w)) < 1e-9:
+            below = grid[grid < w * (1 - 1e-6)]
+            assert below.size == 0 or float(np.min(g(below))) > 1e-7
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=IDS)
+def test_greedy_rule(name, prob):
+    F = fd.setup(prob)
+    w, r, J0 = adi.greedy_parameters(F, 0.1)
+    lams = [f["lam"] for f in F]
+    assert r <= 0.1 and abs(adi.rho(w, lams) - r) <= 1e-12
+    assert len(w) == 1 or adi.rho(w[:-1], lams) > 0.1           # stops at the first count meeting eps
+    wd, _, _ = adi.parameters(F, 0.1)
+    assert len(w) <= len(wd)
+    x = synth.random_vector(int(np.prod([len(l) for l in lams])), 9)
+    assert np.linalg.norm(adi.apply(F, x, w) - adi.closed_form(F, x, w)) <= 1e-12 * np.linalg.norm(adi.closed_form(F, x, w))
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_greedy_steps_on_the_cube_match_the_paper(p):
+    """Table cube prints 57 Douglas steps at h^-1 = 128, p <= 3, for tolerance
+    1e-8, and the text puts the greedy choice about 10-20% below that: the
+    greedy count here must land in that band (one step of slack).  (For
+    p >= 4 the table prints 65 and this greedy takes 48-51 steps, 22-26%
+    fewer: beyond the band, not asserted.)"""
+    import json, os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table_cube_adi.json")))
+    ref = gold["douglas_steps"]["128"][gold["degrees"].index(p)]
+    lo, hi = gold["greedy_band"]
+    F = fd.setup(synth.unit_cube(128, p))
+    w, r, _ = adi.greedy_parameters(F, 1e-8)
+    assert r <= 1e-8
+    assert lo * ref - gold["tolerance_steps"] <= len(w) <= hi * ref + gold["tolerance_steps"], (len(w), ref)
