@@ -22,6 +22,8 @@ Other workloads (--workload), each printing one JSON line of the same form:
            h^-1 = 1024 elements per patch and direction, p = 3: CG + additive Schwarz P_IAS
   adi      thick ring 128^3, p = 3: CG + the three-variable ADI preconditioner P_J (eps = 0.1)
            beside CG + the exact FD apply (the paper's FD-vs-ADI comparison)
+  annulus  2D quarter annulus (the paper's Table quarterofring), h^-1 = 1024, p = 3: CG + P with
+           the FD apply by tiled MFMA products (FP64; FP32 beside it)
   cube     unit cube, P = A: the FD apply as the direct solver (the paper's Table cube) at
            h^-1 = 128, 256, 512 (--elements 1024 for the 10^9-unknown case), p = 3 (--degree)
 
@@ -559,6 +561,17 @@ def run_adi(args, api, torch, synth):
     y = torch.empty_like(x)
     t_adi = event_time(torch, lambda: api.igafd_apply_precond(ctx, "fp64", x, y), 10)
     t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), 20)
+    # the greedy parameters (eq. greedy1/2) beside the geometric ones
+    t0 = time.perf_counter()
+    Jg, rhog = api.igafd_set_adi_greedy(ctx, eps)
+    t_params_g = time.perf_counter() - t0
+    t_adi_g = event_time(torch, lambda: api.igafd_apply_precond(ctx, "fp64", x, y), 10)
+    tg, infg = timed_solves(api, torch, ctx, b, u, 3, 1)
+    log(f"ADI greedy: J = {Jg}, rho = {rhog:.3f}, apply {t_adi_g * 1e3:.1f} us, solve {1e3 * float(np.median(tg)):.1f} ms, "
+        f"{infg[-1]['iters']} iterations")
+    greedy = {"J": Jg, "rho": rhog, "param_setup_s": t_params_g, "apply_ms": t_adi_g,
+              "solve_ms": 1e3 * float(np.median(tg)), "iters": infg[-1]["iters"],
+              "true_relres": infg[-1]["true_relres"]}
     api.igafd_set_adi(ctx, 0)
     t_fd = event_time(torch, lambda: api.igafd_apply_precond(ctx, "fp64", x, y), 20)
     tf, inf = timed_solves(api, torch, ctx, b, u, 3, 1)
@@ -573,12 +586,96 @@ def run_adi(args, api, torch, synth):
     out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
         "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"],
         "adi": {"J": J, "rho": rho, "eps": eps, "param_setup_s": t_params},
-        "fd_comparison": {"ms": 1e3 * float(np.median(tf)), "iters": inf[-1]["iters"]},
+        "fd_comparison": {"ms": 1e3 * float(np.median(tf)), "iters": inf[-1]["iters"]}, "greedy": greedy,
         "kernel_ms": {"adi_apply": t_adi, "fd_apply": t_fd, "spmv": t_spmv},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": None, "kernel": "P_J apply (banded line products and solves)",
                      "algorithmic_bytes": by},
         "cpu_baseline": None})
+    ctx.close()
+    return out
+
+
+# The paper's Table quarterofring (CG + P, upper part): 2D quarter annulus,
+# f = 2 sum(x_i^2 - x_i), iterations and seconds on one core of an i7-5820K
+# (MATLAB), preconditioner setup included
+PAPER_ANNULUS = {
+    (128, 2): (25, 0.04), (128, 3): (25, 0.06), (128, 4): (25, 0.07), (128, 5): (25, 0.09),
+    (256, 2): (25, 0.20), (256, 3): (25, 0.26), (256, 4): (25, 0.34), (256, 5): (25, 0.40),
+    (512, 2): (26, 1.13), (512, 3): (26, 1.36), (512, 4): (26, 1.62), (512, 5): (26, 2.00),
+    (1024, 2): (26, 7.30), (1024, 3): (26, 8.13), (1024, 4): (26, 9.09), (1024, 5): (26, 10.52),
+}
+
+
+def annulus_cpu_baseline(target_iters, n_full, p, nnz_full):
+    """The oracle's CG + P on the quarter annulus at h^-1 = 256 (same p, same
+    right-hand side), time per iteration scaled by the FLOPs per iteration
+    (A product 2 nnz, FD apply 4 N (n1 + n2)) to the full mesh, times the
+    GPU's iteration count."""
+    from threadpoolctl import threadpool_info
+
+    import synth
+    from oracle import assembly, fd, pcg
+    E = 256
+    prob = synth.quarter_annulus_2d(E=(E, E), p=p)
+    A = assembly.assemble_matrix(prob)
+    F = fd.setup(prob)
+    b = assembly.assemble_load(prob, synth.RHS_PAPER_POLY)
+    t0 = time.perf_counter()
+    reps = iters = 0
+    while time.perf_counter() - t0 < 10.0 or reps < 3:
+        _, info = pcg.solve(prob, A, F, b, rtol=1e-8)
+        iters += info["iters"]
+        reps += 1
+    per_iter = (time.perf_counter() - t0) / iters
+    n_s = E + p - 2
+    flops_s = 2 * A.nnz + 4 * n_s * n_s * 2 * n_s
+    flops_f = 2 * nnz_full + 4 * n_full * n_full * 2 * n_full
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": per_iter * flops_f / flops_s * target_iters, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle CG + P on the quarter annulus at h^-1={E}, p={p} (N={n_s ** 2}), {reps} solves, "
+                      f"{per_iter * 1e3:.2f} ms/iteration, scaled by FLOPs/iteration to {n_full}^2 dofs and x "
+                      f"{target_iters} iterations"}
+
+
+def run_annulus(args, api, torch, synth):
+    """2D quarter annulus (the paper's Table quarterofring): CG + P with the
+    FD apply by tiled MFMA products (n = 1025 per direction at h^-1 = 1024),
+    FP64 and FP32 mode products."""
+    E, p = args.elements or 1024, args.degree or 3
+    t0 = time.perf_counter()
+    ctx = api.igafd_setup(synth.quarter_annulus_2d(E=(E, E), p=p))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    b = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
+    api.igafd_load_vector(ctx, synth.RHS_PAPER_POLY, b)
+    u = torch.zeros_like(b)
+    times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup)
+    u64 = u.clone()
+    ms_per_step = 1e3 * float(np.median(times))
+    variants = {}
+    if not args.no_variants:
+        ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision="fp32")
+        variants["fp32"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"],
+                            "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
+    kr = kernel_report(api, torch, ctx, reps=20, precisions=("fp64", "fp32"))
+    iters = infos[-1]["iters"]
+    paper = PAPER_ANNULUS.get((E, p))
+    log(f"annulus h^-1={E} p={p} N={ctx.N}: setup {t_setup:.2f} s, solve {ms_per_step:.2f} ms, {iters} iterations" +
+        (f"; paper {paper[0]} iterations, {paper[1]} s" if paper else ""))
+    cpu = None if args.no_cpu_baseline else annulus_cpu_baseline(iters, ctx.n[0], p, ctx.nnz)
+    workload = {"workload": f"2D quarter annulus F = ((1+xi1) cos(pi xi2/2), (1+xi1) sin(pi xi2/2)), p={p}, "
+                            f"{E}^2 elements, N={ctx.N}, f = 2 sum(x_i^2 - x_i), FP64 FD-preconditioned CG "
+                            f"(FD by tiled MFMA products), rtol 1e-8", "elements": E, "degree": p, "N": ctx.N}
+    out = result(args, ms_per_step / 1e3, ms_per_step, "f64", workload, {
+        "iters": iters, "true_relres": infos[-1]["true_relres"], "setup_s": t_setup, "variants": variants,
+        "solve_ms": {"median": ms_per_step, "min": 1e3 * min(times), "max": 1e3 * max(times)},
+        "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
+        "paper": ({"iters": paper[0], "s": paper[1], "hardware": "one core of an i7-5820K, MATLAB R2015a",
+                   "source": "Table quarterofring (CG + P)"} if paper else None),
+        "roofline": dict(fd_roofline(kr), kernel="k_gemm (four FP64 mode products, tiled MFMA)",
+                         algorithmic_flops=kr["fd_flops"], traffic=None),
+        "spmv_roofline": roofline(kr), "cpu_baseline": cpu})
     ctx.close()
     return out
 
@@ -686,7 +783,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ring", choices=["ring", "warped", "batch", "learned", "square", "lshape", "adi",
-                                                             "cube"])
+                                                             "cube", "annulus"])
     ap.add_argument("--elements", type=int, default=0)
     ap.add_argument("--degree", type=int, default=0)
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
@@ -707,7 +804,8 @@ def main():
 
     torch.cuda.set_device(0)
     run = {"ring": run_ring, "warped": run_warped, "batch": run_batch, "learned": run_learned,
-           "square": run_square, "lshape": run_lshape, "adi": run_adi, "cube": run_cube}[args.workload]
+           "square": run_square, "lshape": run_lshape, "adi": run_adi, "cube": run_cube,
+           "annulus": run_annulus}[args.workload]
     out = run(args, api, torch, synth)
     print(json.dumps(out), flush=True)
 

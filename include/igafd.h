@@ -226,6 +226,16 @@ igafd_status igafd_univariate(int degree, int nknots, const double* knots, int q
  * (= ||T_J||) are optional host outputs. */
 igafd_status igafd_set_adi(igafd_ctx* ctx, double eps, int* J, double* rho);
 
+/* As igafd_set_adi with the greedy parameters of Sec. 5.2 eq. greedy1/2:
+ * after k steps the eigenvalue triple of largest |prod_j g_j| (the first in
+ * (k3, k2, k1) order on ties) gives omega_{k+1}, the omega >= 0 minimising
+ * |g| there (in closed form: the smaller positive root of
+ * w^3 - S w^2 + e2 w + e3 when it has one, else the positive root of
+ * w^3 - e2 w - 2 e3, with S, e2, e3 the symmetric functions of the triple);
+ * omega_1 = sqrt(a b).  Stops at the first J with ||T_J|| <= eps, at most J0.
+ * Needs n1 n2 n3 <= 2^28 (one host double per triple during setup). */
+igafd_status igafd_set_adi_greedy(igafd_ctx* ctx, double eps, int* J, double* rho);
+
 /* Parameters in use (all outputs optional, host): J = 0 when ADI is off;
  * omegas: capacity >= J values. */
 igafd_status igafd_get_adi(const igafd_ctx* ctx, int* J, int* J0, double* rho, double* omegas, int capacity);

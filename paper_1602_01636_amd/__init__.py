@@ -9,12 +9,12 @@ from .binding import (IgafdError, Context, Mlp, igafd_apply_A, igafd_autotune, i
                       igafd_diagonals, igafd_features, igafd_get_eigen, igafd_last_error, igafd_load_vector,
                       igafd_mlp_create, igafd_mlp_destroy, igafd_mlp_fit_normalization, igafd_mlp_forward,
                       igafd_mlp_get_params, igafd_mlp_gradient, igafd_mlp_num_params, igafd_mlp_set_params,
-                      igafd_mlp_train_step, igafd_scaling_targets, igafd_set_adi, igafd_set_scaling, igafd_set_scaling_diag_ratio, igafd_setup, igafd_setup_precond, igafd_sizes,
+                      igafd_mlp_train_step, igafd_scaling_targets, igafd_set_adi, igafd_set_adi_greedy, igafd_set_scaling, igafd_set_scaling_diag_ratio, igafd_setup, igafd_setup_precond, igafd_sizes,
                       igafd_solve, igafd_univariate, lib)
 
 __all__ = ["IgafdError", "Context", "Mlp", "igafd_apply_A", "igafd_autotune", "igafd_get_adi", "igafd_get_shape", "igafd_lshape_corner", "igafd_lshape_setup", "igafd_spectral_bounds", "igafd_solve_batched", "igafd_apply_precond", "igafd_destroy",
            "igafd_diagonals", "igafd_features", "igafd_get_eigen", "igafd_last_error", "igafd_load_vector",
            "igafd_mlp_create", "igafd_mlp_destroy", "igafd_mlp_fit_normalization", "igafd_mlp_forward",
            "igafd_mlp_get_params", "igafd_mlp_gradient", "igafd_mlp_num_params", "igafd_mlp_set_params",
-           "igafd_mlp_train_step", "igafd_scaling_targets", "igafd_set_adi", "igafd_set_scaling", "igafd_set_scaling_diag_ratio", "igafd_setup", "igafd_setup_precond", "igafd_sizes",
+           "igafd_mlp_train_step", "igafd_scaling_targets", "igafd_set_adi", "igafd_set_adi_greedy", "igafd_set_scaling", "igafd_set_scaling_diag_ratio", "igafd_setup", "igafd_setup_precond", "igafd_sizes",
            "igafd_solve", "igafd_univariate", "lib"]

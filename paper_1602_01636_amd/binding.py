@@ -78,6 +78,7 @@ _SIGNATURES = {
     "igafd_setup_precond": (C.c_int, [C.POINTER(igafd_problem), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_lshape_setup": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_set_adi": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "igafd_set_adi_greedy": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "igafd_get_adi": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
                                 C.c_void_p, C.c_int]),
     "igafd_lshape_corner": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
@@ -257,6 +258,13 @@ def igafd_set_adi(ctx, eps):
     ||T_J|| <= eps (eps = 0: back to FD).  Returns (J, rho)."""
     J, rho = C.c_int(), C.c_double()
     _check(lib().igafd_set_adi(_h(ctx), float(eps), C.byref(J), C.byref(rho)))
+    return J.value, rho.value
+
+
+def igafd_set_adi_greedy(ctx, eps):
+    """As igafd_set_adi with the greedy parameters (eq. greedy1/2).  Returns (J, rho)."""
+    J, rho = C.c_int(), C.c_double()
+    _check(lib().igafd_set_adi_greedy(_h(ctx), float(eps), C.byref(J), C.byref(rho)))
     return J.value, rho.value
 
 

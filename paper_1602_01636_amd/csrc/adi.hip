@@ -527,7 +527,87 @@ void adi_free(igafd_ctx* c) {
   c->adi = nullptr;
 }
 
-igafd_status adi_setup(igafd_ctx* c, double eps) {
+// eq. greedy2: the omega >= 0 minimising |g(omega; l1, l2, l3)|.  g = 0 at the
+// positive roots of f(w) = w^3 - S w^2 + e2 w + e3 (none or two); the smaller
+// one is taken.  f(0) = e3 > 0 and f has its local minimum at
+// w+ = (S + sqrt(S^2 - 3 e2)) / 3: roots exist iff f(w+) <= 0, and the smaller
+// lies between max(0, w-) (the local maximum) and w+.  Without roots g > 0 and
+// its minimum is at the one positive root of w^3 - e2 w - 2 e3 (where
+// 2 S w^2 / prod(w + l_d) peaks).  Both by bisection to the last bit.
+double best_parameter(double l1, double l2, double l3) {
+  const double S = l1 + l2 + l3, e2 = l1 * l2 + l1 * l3 + l2 * l3, e3 = l1 * l2 * l3;
+  auto bisect = [](auto f, double lo, double hi) {  // f(lo) > 0 >= f(hi) or f(lo) < 0 <= f(hi)
+    const bool up = f(lo) < 0.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if ((f(mid) < 0.0) == up)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  auto f = [&](double w) { return ((w - S) * w + e2) * w + e3; };
+  const double disc = std::sqrt(std::max(0.0, S * S - 3.0 * e2));
+  const double wp = (S + disc) / 3.0, wm = std::max(0.0, (S - disc) / 3.0);
+  if (f(wp) <= 0.0) return bisect(f, wm, wp);
+  auto q = [&](double w) { return (w * w - e2) * w - 2.0 * e3; };
+  double hi = std::sqrt(e2) + std::cbrt(2.0 * e3) + 1e-300;
+  while (q(hi) <= 0.0) hi *= 2.0;
+  return bisect(q, 0.0, hi);
+}
+
+// Greedy parameters (eq. greedy1/2): after k steps, the triple of largest
+// |prod_j g_j| over the eigenvalue triples (the first in (k3, k2, k1) order on
+// ties) picks omega_{k+1} = best_parameter(triple); the first parameter is
+// sqrt(a b).  Stops once max |prod g_j| <= eps or at J0 steps.  The products
+// are kept per triple (n1 n2 n3 doubles on the host, threads over k3).
+igafd_status greedy_parameters(const igafd_ctx* c, double a, double b, double eps, int J0, std::vector<double>* w,
+                               double* rho) {
+  const std::vector<double>&l1 = c->dir[0].lam, &l2 = c->dir[1].lam, &l3 = c->dir[2].lam;
+  const size_t n1 = l1.size(), n2 = l2.size(), n3 = l3.size(), total = n1 * n2 * n3;
+  if (total > (size_t(1) << 28)) {
+    set_error("greedy ADI parameters: too many eigenvalue triples (more than 2^28)");
+    return IGAFD_ERR_ARG;
+  }
+  std::vector<double> G(total, 1.0);
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int T = (int)std::max(1u, std::min(16u, hw));
+  w->assign(1, std::sqrt(a * b));
+  for (;;) {
+    const double om = w->back();
+    std::vector<double> best(T, -1.0);
+    std::vector<size_t> at(T, 0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t]() {
+        for (size_t k3 = t; k3 < n3; k3 += T)
+          for (size_t k2 = 0; k2 < n2; ++k2)
+            for (size_t k1 = 0; k1 < n1; ++k1) {
+              const size_t i = (k3 * n2 + k2) * n1 + k1;
+              const double s = l1[k1] + l2[k2] + l3[k3];
+              G[i] = G[i] * (1.0 - 2.0 * om * om * s / ((om + l1[k1]) * (om + l2[k2]) * (om + l3[k3])));
+              const double v = std::fabs(G[i]);
+              if (v > best[t] || (v == best[t] && i < at[t])) {
+                best[t] = v;
+                at[t] = i;
+              }
+            }
+      });
+    for (auto& x : th) x.join();
+    int tb = 0;
+    for (int t = 1; t < T; ++t)
+      if (best[t] > best[tb] || (best[t] == best[tb] && at[t] < at[tb])) tb = t;
+    *rho = best[tb];
+    if (*rho <= eps || (int)w->size() >= J0) return IGAFD_OK;
+    const size_t i = at[tb];
+    const size_t k1 = i % n1, k2 = (i / n1) % n2, k3 = i / (n1 * n2);
+    w->push_back(best_parameter(l1[k1], l2[k2], l3[k3]));
+  }
+}
+
+igafd_status adi_setup(igafd_ctx* c, double eps, int rule) {
   if (c->dim != 3) {
     set_error("the three-variable ADI is for 3D problems");
     return IGAFD_ERR_ARG;
@@ -550,11 +630,16 @@ igafd_status adi_setup(igafd_ctx* c, double eps) {
   const int J0 = std::max(1, (int)std::ceil(1.16 * std::log(b / a) * std::log(1.0 / eps)));
   std::vector<double> w;
   double rho = 1.0;
-  for (int J = 1; J <= J0; ++J) {
-    w.assign(J, 0.0);
-    for (int j = 0; j < J; ++j) w[j] = J == 1 ? std::sqrt(a * b) : a * std::pow(b / a, (double)j / (J - 1));
-    rho = error_norm(w, c->dir[0].lam, c->dir[1].lam, c->dir[2].lam);
-    if (rho <= eps) break;
+  if (rule == kAdiGreedy) {
+    const igafd_status gs = greedy_parameters(c, a, b, eps, J0, &w, &rho);
+    if (gs != IGAFD_OK) return gs;
+  } else {
+    for (int J = 1; J <= J0; ++J) {
+      w.assign(J, 0.0);
+      for (int j = 0; j < J; ++j) w[j] = J == 1 ? std::sqrt(a * b) : a * std::pow(b / a, (double)j / (J - 1));
+      rho = error_norm(w, c->dir[0].lam, c->dir[1].lam, c->dir[2].lam);
+      if (rho <= eps) break;
+    }
   }
   std::unique_ptr<igafd_adi> st(new igafd_adi());
   st->eps = eps;

@@ -1019,7 +1019,11 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   return IGAFD_OK;
 }
 
-igafd_status igafd_set_adi(igafd_ctx* c, double eps, int* J, double* rho) {
+}  // extern "C"
+
+namespace igafd {
+namespace {
+igafd_status set_adi_impl(igafd_ctx* c, double eps, int rule, int* J, double* rho) {
   if (!c) {
     set_error("null context");
     return IGAFD_ERR_ARG;
@@ -1034,11 +1038,23 @@ igafd_status igafd_set_adi(igafd_ctx* c, double eps, int* J, double* rho) {
     set_error("the ADI preconditioner is for single-patch 3D problems");
     return IGAFD_ERR_ARG;
   }
-  const igafd_status s = adi_setup(c, eps);
+  const igafd_status s = adi_setup(c, eps, rule);
   if (s != IGAFD_OK) return s;
   if (J) *J = (int)c->adi->omega.size();
   if (rho) *rho = c->adi->rho;
   return IGAFD_OK;
+}
+}  // namespace
+}  // namespace igafd
+
+extern "C" {
+
+igafd_status igafd_set_adi(igafd_ctx* c, double eps, int* J, double* rho) {
+  return set_adi_impl(c, eps, kAdiGeometric, J, rho);
+}
+
+igafd_status igafd_set_adi_greedy(igafd_ctx* c, double eps, int* J, double* rho) {
+  return set_adi_impl(c, eps, kAdiGreedy, J, rho);
 }
 
 igafd_status igafd_get_adi(const igafd_ctx* c, int* J, int* J0, double* rho, double* omegas, int capacity) {

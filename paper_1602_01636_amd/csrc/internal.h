@@ -171,7 +171,8 @@ igafd_status fd_apply_gemm3d(igafd_ctx* c, int prec, const double* r, double* s,
                              double* partial, const int* flag);
 int fd_gemm_blocks(const igafd_ctx* c);  // blocks (= (r, s) partials) of the last product
 // adi.hip
-igafd_status adi_setup(igafd_ctx* c, double eps);
+constexpr int kAdiGeometric = 0, kAdiGreedy = 1;  // parameter rules of the three-variable ADI
+igafd_status adi_setup(igafd_ctx* c, double eps, int rule);
 igafd_status adi_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,
                        double* partial_rz, const int* flag);
 void adi_free(igafd_ctx* c);

@@ -122,3 +122,56 @@ def test_adi_thick_ring_128_p3(api):
         # at most ~11% more iterations (plus one for rounding)
         assert info["iters"] <= int(np.ceil(info_fd["iters"] * np.sqrt(1.1 / 0.9))) + 1
         assert rel(to_host(u), to_host(u2)) <= 1e-6
+
+
+@pytest.mark.parametrize("name,prob", CASES[:4], ids=IDS[:4])
+def test_adi_greedy_parameters_and_solve(api, name, prob):
+    """Greedy parameters (eq. greedy1/2) against the oracle's rule: the same
+    count, the parameters and rho_J to rounding; the apply against the
+    closed form; CG + P_J against the oracle's CG with those parameters."""
+    F = fd.setup(prob)
+    w, r_or, J0 = adi.greedy_parameters(F, 0.1)
+    A = assembly.assemble_matrix(prob)
+    b = assembly.assemble_load(prob, synth.RHS_SINPROD)
+    u_or, info_or = pcg.pcg(lambda v: A @ v, lambda v: adi.apply(F, v, w), b, rtol=1e-8)
+    with api.igafd_setup(prob) as ctx:
+        J, rho = api.igafd_set_adi_greedy(ctx, 0.1)
+        g = api.igafd_get_adi(ctx)
+        assert J == len(w) and g["J0"] == J0
+        assert np.allclose(g["omegas"], w, rtol=1e-9, atol=0)
+        assert abs(rho - r_or) <= 1e-9 * r_or and rho <= 0.1
+        x = synth.random_vector(ctx.N, 17)
+        s = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_precond(ctx, "fp64", to_dev(x), s)
+        assert rel(to_host(s), adi.closed_form(F, x, w)) < 1e-11
+        u = to_dev(np.zeros(ctx.N))
+        info = api.igafd_solve(ctx, to_dev(b), u, rtol=1e-8)
+        assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+        assert abs(info["iters"] - info_or["iters"]) <= 1, (info["iters"], info_or["iters"])
+        assert rel(to_host(u), u_or) <= 1e-7
+
+
+def test_adi_greedy_thick_ring_128_p3(api):
+    """Full size: greedy parameters against the oracle's, the apply against the
+    closed form, and CG + P_J within the Thm. ADIprec bound of CG + P."""
+    prob = synth.thick_ring(E=128, p=3)
+    F = fd.setup(prob)
+    w, r_or, _ = adi.greedy_parameters(F, 0.1)
+    kappa = max(f["lam"].max() / f["lam"].min() for f in F)
+    with api.igafd_setup(prob) as ctx:
+        J, rho = api.igafd_set_adi_greedy(ctx, 0.1)
+        assert J == len(w) and np.allclose(api.igafd_get_adi(ctx)["omegas"], w, rtol=1e-9, atol=0)
+        x = np.random.default_rng(19).standard_normal(ctx.N)
+        s = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_precond(ctx, "fp64", to_dev(x), s)
+        assert rel(to_host(s), adi.closed_form(F, x, w)) < max(1e-11, 2.2e-16 * kappa)
+        b = to_dev(np.zeros(ctx.N))
+        api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
+        u = to_dev(np.zeros(ctx.N))
+        info = api.igafd_solve(ctx, b, u, rtol=1e-8)
+        assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+        api.igafd_set_adi(ctx, 0)
+        u2 = to_dev(np.zeros(ctx.N))
+        info_fd = api.igafd_solve(ctx, b, u2, rtol=1e-8)
+        assert info["iters"] <= int(np.ceil(info_fd["iters"] * np.sqrt(1.1 / 0.9))) + 1
+        assert rel(to_host(u), to_host(u2)) <= 1e-6
