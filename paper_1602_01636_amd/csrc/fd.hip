@@ -328,7 +328,12 @@ __device__ inline int row_of(int grp, int r) {
 
 constexpr int kSliceCols = 48;  // output columns (k1) per slice block
 constexpr int kDir3Cols = 32;   // columns (i2, i1) per direction-3 block
-constexpr int kMaxTilesPerWave = 3;
+// waves per block of the fused passes; a direction of up to 160 (10 row
+// tiles of 16) gives each wave at most kMaxTilesPerWave tiles
+constexpr int kFusedWaves = 4;
+constexpr int kFusedThreads = 64 * kFusedWaves;
+constexpr int kMaxTilesPerWave = (10 + kFusedWaves - 1) / kFusedWaves;
+static_assert(kFusedWaves * kMaxTilesPerWave >= 10, "row-tile slots");
 
 // row length of the transposed LDS tile (a multiple of 16 bytes)
 template <typename T>
@@ -369,8 +374,8 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
       }
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        if (on && wave + 4 * m < mtiles)
-          loadA1(k, wave + 4 * m, a[u][m]);
+        if (on && wave + kFusedWaves * m < mtiles)
+          loadA1(k, wave + kFusedWaves * m, a[u][m]);
         else
           zero4(a[u][m]);
       }
@@ -390,8 +395,8 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
       }
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        if (on && wave + 4 * m < mtiles)
-          loadA2(k, wave + 4 * m, a[u][m]);
+        if (on && wave + kFusedWaves * m < mtiles)
+          loadA2(k, wave + kFusedWaves * m, a[u][m]);
         else
           zero4(a[u][m]);
       }
@@ -404,7 +409,7 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
       if constexpr (Pr::KPL == 1) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-          if (wave + 4 * m < mtiles) {
+          if (wave + kFusedWaves * m < mtiles) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) grp_mma<Pr>(a[u][m], b[u][t], acc[m][t]);
           }
@@ -418,7 +423,7 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
           pb[t] = s4_t{to_bf16(b[u][t][0]), to_bf16(b[u][t][1]), to_bf16(b[u][t][2]), to_bf16(b[u][t][3])};
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-          if (wave + 4 * m < mtiles) {
+          if (wave + kFusedWaves * m < mtiles) {
 #pragma unroll
             for (int t = 0; t < NT; ++t)
               acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[m], pb[t], acc[m][t], 0, 0, 0);
@@ -443,7 +448,7 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
   if (SYNC_MID) __syncthreads();
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
-    const int mt = wave + 4 * m;
+    const int mt = wave + kFusedWaves * m;
     if (mt >= mtiles) break;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -472,7 +477,7 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
 // slice blockIdx.y and output columns k1 in [blockIdx.x * 48, +48).  X, Out:
 // slice-contiguous (n2 x n1); V1, V2 row-major, zero padded to npad1, npad2.
 template <class Pr, typename Tin, typename Tout, typename Tw, typename Tmid>
-__global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
+__global__ __launch_bounds__(kFusedThreads) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
                                                   const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
                                                   int npad1, int npad2, Epi ep) {
   using acc_t = typename Pr::acc;
@@ -528,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tou
   double dot = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
-    const int mt = wave + 4 * m;
+    const int mt = wave + kFusedWaves * m;
     if (mt >= mtiles) break;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -546,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tou
       }
   }
   if (ep.flags & EPI_DOT) {
-    const double sum = block_sum(dot);
+    const double sum = block_sum<kFusedThreads>(dot);
     if (threadIdx.x == 0) ep.partial[blockIdx.x + (long long)gridDim.x * blockIdx.y] = sum;
   }
 }
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_slice(const Tin* __restrict__ X, Tou
 // Pass B: Out[i3][c] = sum_k3 Wb[i3][k3] (sum_j3 Wf[k3][j3] X[j3][c]) / lamsum(k3, c)
 // for the 32 columns c of block blockIdx.x (c = i2 n1 + i1, C = n1 n2).
 template <class Pr, typename Tw, typename Tmid>
-__global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
+__global__ __launch_bounds__(kFusedThreads) void k_dir3(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
                                                  const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
                                                  int npad3, Epi ep) {
   using acc_t = typename Pr::acc;
@@ -575,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmi
   {
     constexpr int VEC = 16 / (int)sizeof(Tmid), PER_ROW = kDir3Cols / VEC;
     const int rows = mtiles * 16;
-    for (int idx = threadIdx.x; idx < rows * PER_ROW; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < rows * PER_ROW; idx += kFusedThreads) {
       const int j3 = idx / PER_ROW, cq = (idx - j3 * PER_ROW) * VEC;
       const int c = c0 + cq;
       Tmid v[VEC];
@@ -613,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmi
   two_step<Pr, NT, true>(acc, n3, n3, mtiles, wave, grp, col, sT, ldt, loadA1, loadB1, mid, loadA2);
 #pragma unroll
   for (int m = 0; m < kMaxTilesPerWave; ++m) {
-    const int mt = wave + 4 * m;
+    const int mt = wave + kFusedWaves * m;
     if (mt >= mtiles) break;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -626,8 +631,9 @@ __global__ __launch_bounds__(kBlock) void k_dir3(const Tmid* __restrict__ X, Tmi
   }
 }
 
-// the fused path needs each direction's row tiles to fit 4 waves x 3 tiles
-// and the LDS tile of a slice pass within 64 KB (n2 <= 160 in FP64)
+// the fused path needs each direction's row tiles (at most 10) to fit the
+// waves' tile slots and the LDS tile of a slice pass within 64 KB (n2 <= 160
+// in FP64)
 bool fused_ok(const igafd_ctx* c) {
   return c->dim == 3 && c->n[0] <= 160 && c->n[1] <= 160 && c->n[2] <= 160;
 }
@@ -667,13 +673,13 @@ igafd_status apply_fused(igafd_ctx* c, const Tw* const* Wf, const Tw* const* Wb,
   const size_t lds_s = sizeof(T) * (size_t)kSliceCols * lds_ld<T>((n2 + 15) / 16);
   const size_t lds_3 = sizeof(T) * (size_t)kDir3Cols * lds_ld<T>((n3 + 15) / 16);
   const int C = n1 * n2;
-  hipLaunchKernelGGL((k_slice<Pr, double, T, Tw, T>), gs, dim3(kBlock), lds_s, st, r, b0, Wf[0], Wf[1], n1, n2,
+  hipLaunchKernelGGL((k_slice<Pr, double, T, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, r, b0, Wf[0], Wf[1], n1, n2,
                      d[0].npad, d[1].npad, e_in);
   IGAFD_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_dir3<Pr, Tw, T>), dim3((unsigned)((C + kDir3Cols - 1) / kDir3Cols)), dim3(kBlock), lds_3, st,
+  hipLaunchKernelGGL((k_dir3<Pr, Tw, T>), dim3((unsigned)((C + kDir3Cols - 1) / kDir3Cols)), dim3(kFusedThreads), lds_3, st,
                      b0, b1, Wf[2], Wb[2], n3, C, d[2].npad, e_lam);
   IGAFD_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_slice<Pr, T, double, Tw, T>), gs, dim3(kBlock), lds_s, st, b1, s, Wb[0], Wb[1], n1, n2,
+  hipLaunchKernelGGL((k_slice<Pr, T, double, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, b1, s, Wb[0], Wb[1], n1, n2,
                      d[0].npad, d[1].npad, e_out);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;

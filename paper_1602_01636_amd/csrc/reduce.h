@@ -11,9 +11,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum over a block of kBlock threads; the result is valid in thread 0.
+// Sum over a block of NTH threads; the result is valid in thread 0.
+template <int NTH = kBlock>
 __device__ inline double block_sum(double v) {
-  __shared__ double part[kBlock / 64];
+  __shared__ double part[NTH / 64];
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -21,7 +22,7 @@ __device__ inline double block_sum(double v) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+    for (int w = 0; w < NTH / 64; ++w) s += part[w];
   return s;
 }
 
