@@ -139,6 +139,12 @@ constexpr int kTileMaxCh = 8;  // row pairs per thread (chunks of 256 pairs)
 // largest chunk count per degree that the compiler keeps in registers
 constexpr int kTileMaxChP[kMaxDegree + 1] = {0, 8, 8, 8, 4, 1, 1};
 
+// Tiles of at most this many chunks (per degree) keep the scatter's x window
+// of their own rows (the same for every line offset) in registers instead of
+// reloading it per offset: 4(p+1) VGPRs per chunk, within the 256 of two waves
+// per SIMD without spilling.
+constexpr int kXsRegMaxChP[kMaxDegree + 1] = {0, 8, 4, 4, 2, 1, 1};
+
 // chunks of 256 row pairs of a B2 x B3 tile
 inline int tile_chunks(int b2, int b3, int n1) { return ((b2 * b3 * n1 + 1) / 2 + kBlock - 1) / kBlock; }
 
@@ -180,7 +186,8 @@ template <int P, int CH, bool CENTER>
 __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restrict__ band, long long Ns,
                                           const double* __restrict__ x, double* lds, int n1, long long n12, int E2,
                                           int trash, unsigned own, const unsigned (&go)[CH], const int (&tb)[CH],
-                                          d2_t (&acc)[CH]) {
+                                          d2_t (&acc)[CH], const d2_t (&xw)[CH][P + 1]) {
+  constexpr bool XREG = CH <= kXsRegMaxChP[P];
   constexpr int W = 2 * P + 1;
   constexpr int CTR = (W * W * W - 1) / 2;
   constexpr int LO = CENTER ? 0 : -P;
@@ -191,7 +198,8 @@ __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restri
   // lane offset" per line offset instead of per-lane pointer induction
   // variables carried across offsets (one per chunk and o1, too many
   // registers); the scatter's x window, the same for every offset, is
-  // reloaded (an L1 hit) rather than kept in registers.
+  // reloaded (an L1 hit) unless the tile is small enough to keep it in
+  // registers (xw).
   const gbytes xsb = opaque(x), xgb = opaque(xg), bpb = opaque(bp0);
   const long long plane = 8 * Ns;
   auto load = [&](int m, ChunkVals<P>& v) {
@@ -205,18 +213,19 @@ __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restri
 #pragma unroll
     for (int k = 0; k <= P; ++k) {
       v.xg[k] = ld2(xgb, g, 2 * k - P);
-      v.xs[k] = ld2(xsb, g, 2 * k - P);
+      if (!XREG) v.xs[k] = ld2(xsb, g, 2 * k - P);
     }
   };
   auto compute = [&](int m, const ChunkVals<P>& v) {
+    const d2_t* xs = XREG ? xw[m] : v.xs;
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int o1 = LO; o1 <= P; ++o1) {
       acc[m].x = fma(v.bg[o1 + P].x, el(v.xg, o1 + P), acc[m].x);
       acc[m].y = fma(v.bg[o1 + P].y, el(v.xg, o1 + P + 1), acc[m].y);
       if (!CENTER || o1 > 0) {
-        s0 = fma(v.bs[o1 + P].x, el(v.xs, P - o1), s0);
-        s1 = fma(v.bs[o1 + P].y, el(v.xs, P - o1 + 1), s1);
+        s0 = fma(v.bs[o1 + P].x, el(xs, P - o1), s0);
+        s1 = fma(v.bs[o1 + P].y, el(xs, P - o1 + 1), s1);
       }
     }
     if (CENTER) {
@@ -282,18 +291,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     own |= (ok1 ? 2u : 0u) << (2 * m);
   }
   const int trash = elems;
-  tile_pair<P, CH, true>(0, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+  // the scatter's x window of the own rows (register-held tiles only)
+  d2_t xw[CH][P + 1];
+  if constexpr (CH <= kXsRegMaxChP[P]) {
+    const gbytes xb = opaque(x);
+#pragma unroll
+    for (int m = 0; m < CH; ++m)
+#pragma unroll
+      for (int k = 0; k <= P; ++k) xw[m][k] = ld2(xb, go[m], 2 * k - P);
+  }
+  tile_pair<P, CH, true>(0, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc, xw);
   __syncthreads();  // accumulator zeroed
 #pragma unroll 1
   for (int o2 = 1; o2 <= P; ++o2) {
-    tile_pair<P, CH, false>(o2, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+    tile_pair<P, CH, false>(o2, 0, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc, xw);
     __syncthreads();
   }
 #pragma unroll 1
   for (int o3 = 1; o3 <= P; ++o3)
 #pragma unroll 1
     for (int o2 = -P; o2 <= P; ++o2) {
-      tile_pair<P, CH, false>(o2, o3, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc);
+      tile_pair<P, CH, false>(o2, o3, band, Ns, x, lds, n1, n12, E2, trash, own, go, tb, acc, xw);
       __syncthreads();
     }
   // own rows: no other lane writes them in this phase
