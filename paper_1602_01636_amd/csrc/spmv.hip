@@ -142,8 +142,9 @@ constexpr int kTileMaxChP[kMaxDegree + 1] = {0, 8, 8, 8, 4, 1, 1};
 // Tiles of at most this many chunks (per degree) keep the scatter's x window
 // of their own rows (the same for every line offset) in registers instead of
 // reloading it per offset: 4(p+1) VGPRs per chunk, within the 256 of two waves
-// per SIMD without spilling.
-constexpr int kXsRegMaxChP[kMaxDegree + 1] = {0, 8, 4, 4, 2, 1, 1};
+// per SIMD.  At p = 3 five chunks spill 36 bytes per lane and still gain
+// (fewer address operations); at p = 4 three chunks would spill 244.
+constexpr int kXsRegMaxChP[kMaxDegree + 1] = {0, 8, 4, 5, 2, 1, 1};
 
 // chunks of 256 row pairs of a B2 x B3 tile
 inline int tile_chunks(int b2, int b3, int n1) { return ((b2 * b3 * n1 + 1) / 2 + kBlock - 1) / kBlock; }
