@@ -489,8 +489,11 @@ bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b
       const long long tiles = (long long)((n2 + b2 - 1) / b2) * ((n3 + b3 - 1) / b3);
       const long long slots = (long long)cus * std::max(1LL, (long long)lds_cu / lds);
       const long long rounds = (tiles + slots - 1) / slots;
-      const double score = (double)lines / (double)e * ((double)lines * n1 / 2.0 / (ch * kBlock)) *
-                           ((double)tiles / (double)(rounds * slots));
+      double score = (double)lines / (double)e * ((double)lines * n1 / 2.0 / (ch * kBlock)) *
+                     ((double)tiles / (double)(rounds * slots));
+      // shapes that keep the own-row x window in registers issue fewer loads
+      // per line offset (p = 4, 112^3: 4 x 2 lines 887 us against 4 x 3, 968 us)
+      if (p >= 3 && ch <= kXsRegMaxChP[p]) score *= 1.2;
       if (score > best * (1.0 + 1e-9)) {
         best = score;
         *b2_out = b2;
