@@ -700,12 +700,13 @@ int dot_blocks_for(const igafd_ctx* c) {
   return grid_x(C, 1, ms.nblk);
 }
 
-// Applies with long directions use the tiled products of gemm.hip (FP64 and
-// FP32): 2D grids with n1 + n2 >= 384, 3D tensors with a direction longer
-// than the fused passes take.  IGAFD_FD_GEMM=0/1 at setup forces the choice.
+// Applies with long directions use the tiled products of gemm.hip (FP64, FP32
+// and BF16 operands): 2D grids with n1 + n2 >= 384, 3D tensors with a direction
+// longer than the fused passes take.  IGAFD_FD_GEMM=0/1 at setup forces the
+// choice.
 constexpr int kGemmAutoN = 384;
 bool use_gemm(const igafd_ctx* c, int prec) {
-  if (prec == IGAFD_BF16) return false;
+  (void)prec;  // the same choice for every precision
   if (c->fd_gemm >= 0) return c->fd_gemm != 0;
   if (c->dim == 3) return !fused_ok(c);
   return c->n[0] + c->n[1] >= kGemmAutoN;
@@ -750,8 +751,8 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
   if ((stt = (x)) != IGAFD_OK) \
     return stt;
   if (c->dim == 3) {
-    if constexpr (!std::is_same<Pr, PBF16>::value) {
-      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : IGAFD_FP32;
+    {
+      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
       if (use_gemm(c, prec)) return fd_apply_gemm3d(c, prec, r, s, S, partial, flag);
     }
     // forward: direction 1 (fast axis), 2, 3 (+ eigenvalue scaling)
@@ -766,8 +767,8 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
                                              (long long)n1 * n2, e0)));
     IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
   } else {
-    if constexpr (!std::is_same<Pr, PBF16>::value) {
-      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : IGAFD_FP32;
+    {
+      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
       if (use_gemm(c, prec)) return fd_apply_gemm2d(c, prec, r, s, S, partial, flag, ldr, lds);
     }
     IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in,
@@ -833,7 +834,7 @@ igafd_status schwarz(igafd_ctx* c, const double* r, double* s, double* partial, 
   s1->fd_tiles = s2->fd_tiles = c->fd_tiles;
   igafd_status st;
   constexpr int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
-  if (prec != IGAFD_BF16 && use_gemm(s1, prec) && use_gemm(s2, prec)) {
+  if (use_gemm(s1, prec) && use_gemm(s2, prec)) {
     // both subdomain applies by tiled products, each pass of the two in one launch
     st = fd_apply_gemm2d_pair(prec, s2, r, n, s, n, s1, r, n, c->fdbuf[0], h, flag);
     if (st != IGAFD_OK) return st;

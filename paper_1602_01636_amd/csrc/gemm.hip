@@ -42,12 +42,34 @@ struct G64 {
   using V = double;
   using acc = gd4_t;
   static constexpr bool ROW_STRIDE4 = true;
+  static constexpr bool BF16 = false;
 };
 struct G32 {
   using V = float;
   using acc = gf4_t;
   static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool BF16 = false;
 };
+// BF16 operands, FP32 accumulation (v_mfma_f32_16x16x16_bf16): the slices are
+// staged in FP32 as for G32; per 16-deep slice each lane rounds four k values
+// of an operand to BF16 and one MFMA covers the slice.  The lane group l/16
+// takes k = l/16 + 4 j (j = 0..3) on both operands (the sum over k does not
+// care which lane holds which k, and LDS rows LA apart hit distinct banks).
+struct G16 {
+  using V = float;
+  using acc = gf4_t;
+  static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool BF16 = true;
+};
+
+typedef short gs4_t __attribute__((ext_vector_type(4)));
+
+// round to nearest even
+__device__ inline short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
 
 __device__ inline gd4_t mma(double a, double b, gd4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -240,6 +262,23 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA,
   auto compute = [&](int buf) {
     const V* as = As + buf * BK * LA;
     const V* bs = Bs + buf * BK * LB;
+    if constexpr (G::BF16) {
+      gs4_t pa[TM], pb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pa[i][j] = bf16_bits(as[(grp + 4 * j) * LA + wm0 + i * 16 + col]);
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pb[t][j] = bf16_bits(bs[(grp + 4 * j) * LB + wn0 + t * 16 + col]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int t = 0; t < TN; ++t)
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[i], pb[t], acc[i][t], 0, 0, 0);
+      return;
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       V a[TM], b[TN];
@@ -432,6 +471,8 @@ template <>
 const double* wm<G64>(const DevDir& d, int which) { return d.W64[which]; }
 template <>
 const float* wm<G32>(const DevDir& d, int which) { return d.W32[which]; }
+template <>
+const float* wm<G16>(const DevDir& d, int which) { return d.W32[which]; }
 
 // One 2D FD apply (Sec. 4.1 Alg. 1) by four products, or two independent
 // ones (contexts c and c1, same precision) whose four passes share launches.
@@ -571,8 +612,10 @@ igafd_status fd_apply_gemm3d(igafd_ctx* c, int prec, const double* r, double* s,
       return apply3d<G64, double>(c, r, s, S, partial, flag);
     case IGAFD_FP32:
       return apply3d<G32, float>(c, r, s, S, partial, flag);
+    case IGAFD_BF16:
+      return apply3d<G16, float>(c, r, s, S, partial, flag);
     default:
-      set_error("internal: tiled products run in FP64 or FP32");
+      set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
   }
 }
@@ -589,8 +632,10 @@ igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s,
       return apply2d<G64, double>(&job, 1, S, partial, flag);
     case IGAFD_FP32:
       return apply2d<G32, float>(&job, 1, S, partial, flag);
+    case IGAFD_BF16:
+      return apply2d<G16, float>(&job, 1, S, partial, flag);
     default:
-      set_error("internal: tiled products run in FP64 or FP32");
+      set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
   }
 }
@@ -607,8 +652,10 @@ igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int
       return apply2d<G64, double>(jobs, 2, nullptr, nullptr, flag);
     case IGAFD_FP32:
       return apply2d<G32, float>(jobs, 2, nullptr, nullptr, flag);
+    case IGAFD_BF16:
+      return apply2d<G16, float>(jobs, 2, nullptr, nullptr, flag);
     default:
-      set_error("internal: tiled products run in FP64 or FP32");
+      set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
   }
 }
