@@ -96,14 +96,16 @@ def kernel_report(api, torch, ctx, reps=50, precisions=("fp64", "fp32", "bf16"))
 def spmv_kernel_name(api, ctx):
     s = api.igafd_get_shape(ctx)
     if s["tile_b2"] > 0:
-        return f"k_spmv_tile<p={ctx.p}> ({s['tile_b2']}x{s['tile_b3']} lines) + k_spmv_combine", "tile"
-    return f"k_spmv<R={s['spmv_rows']}>", "row"
+        return (f"igafd_apply_A: k_copy (x into the zero-halo buffer) + k_spmv_tile<p={ctx.p}> "
+                f"({s['tile_b2']}x{s['tile_b3']} lines) + k_spmv_combine"), "tile"
+    return f"igafd_apply_A: k_copy (x into the zero-halo buffer) + k_spmv<R={s['spmv_rows']}>", "row"
 
 
 def profiled_traffic(kernel_tag, workload_tag):
-    """HBM/fabric bytes per A product from the committed counter summaries
-    (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy), used only
-    while the A-product source is the one that was measured."""
+    """HBM/fabric bytes per A product (one igafd_apply_A: the copy into the
+    zero-halo buffer and the product kernels) from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy),
+    used only while the A-product source is the one that was measured."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1602_01636_amd", "csrc", "spmv.hip")

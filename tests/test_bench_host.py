@@ -30,3 +30,18 @@ def test_paper_tables_quoted_by_the_benchmark():
     for p, row in gold["cube_fd_s"].items():
         for E, sec in row.items():
             assert bench.PAPER_CUBE_FD_S[int(p)][int(E)] == sec
+
+
+def test_committed_counter_summary_matches_the_a_product_source():
+    """The benchmark's roofline.traffic comes from the committed counter
+    summary of the tiled A product only while its source hash matches;
+    a changed source without re-taken counters would report null."""
+    sys.path.insert(0, ROOT)
+    import bench
+    traffic, source = bench.profiled_traffic("tile", "thick_ring E=128 p=3")
+    assert source is not None and source.startswith("profiles")
+    # one igafd_apply_A moves more than its algorithmic bytes (x once, each stored value once)
+    E, p = 128, 3
+    n = E + p
+    N = n ** 3
+    assert traffic > 8 * N * 3 and traffic < 3 * 2.872e9
