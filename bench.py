@@ -77,7 +77,7 @@ def fd_flops(ctx):
     return 4 * ctx.N * sum(ctx.n[:ctx.dim]) + ctx.N
 
 
-def kernel_report(api, torch, ctx, reps=50, precisions=("fp64", "fp32", "bf16")):
+def kernel_report(api, torch, ctx, reps=50, precisions=("fp64", "fp32", "bf16", "bf16x3")):
     """Event-timed A product and FD applies of one context."""
     x = torch.randn(ctx.N, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
@@ -134,7 +134,7 @@ def roofline(kr, workload_tag=None):
 
 
 def fd_roofline(kr, prec="fp64"):
-    peak = {"fp64": FP64_PEAK_TF, "fp32": FP32_PEAK_TF, "bf16": BF16_PEAK_TF}[prec]
+    peak = {"fp64": FP64_PEAK_TF, "fp32": FP32_PEAK_TF, "bf16": BF16_PEAK_TF, "bf16x3": BF16_PEAK_TF}[prec]
     tf = kr["fd_flops"] / kr["t_fd"][prec] / 1e9
     return {"bound": "mfma", "precision": prec, "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak}
 
@@ -273,7 +273,7 @@ def run_ring(args, api, torch, synth):
     kr = kernel_report(api, torch, ctx)
     variants = {}
     if not args.no_variants:
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "bf16x3"):
             ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision=prec)
             err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
             variants[prec] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"],
@@ -321,6 +321,10 @@ def run_warped(args, api, torch, synth):
     variants["fp32"] = {"s": float(np.median(ts32)), "iters": inf32[-1]["iters"],
                         "true_relres": inf32[-1]["true_relres"],
                         "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
+    tsx, infx = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision="bf16x3")
+    variants["bf16x3"] = {"s": float(np.median(tsx)), "iters": infx[-1]["iters"],
+                          "true_relres": infx[-1]["true_relres"],
+                          "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
     times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup, precision="bf16")
     err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
     ms_per_step = 1e3 * sum(times) / len(times)
@@ -510,7 +514,7 @@ def run_lshape(args, api, torch, synth):
     ms_per_step = 1e3 * float(np.median(times))
     variants = {}
     if not args.no_variants:
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "bf16x3"):
             tv, iv = timed_solves(api, torch, ctx, b, u, 3, 1, precision=prec)
             variants[prec] = {"ms": 1e3 * float(np.median(tv)), "iters": iv[-1]["iters"],
                               "true_relres": iv[-1]["true_relres"]}
@@ -518,7 +522,7 @@ def run_lshape(args, api, torch, synth):
     y = torch.empty_like(x)
     t_spmv = event_time(torch, lambda: api.igafd_apply_A(ctx, x, y), 20)
     t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, x, y), 10)
-            for pr in ("fp64", "fp32", "bf16")}
+            for pr in ("fp64", "fp32", "bf16", "bf16x3")}
     nnz_L = lshape_nnz(n, h, p)
     by = 8 * ((nnz_L + ctx.ndofs) // 2) + 16 * ctx.ndofs
     fl = 8 * h * n * (h + n)
@@ -737,7 +741,7 @@ def run_cube(args, api, torch, synth):
         fl = fd_flops(ctx)
         reps = 20 if ctx.N < 5e7 else 5
         t_fd = {pr: event_time(torch, lambda pr=pr: api.igafd_apply_precond(ctx, pr, r, s), reps)
-                for pr in ("fp64", "fp32", "bf16")}
+                for pr in ("fp64", "fp32", "bf16", "bf16x3")}
         tf = {pr: fl / t / 1e9 for pr, t in t_fd.items()}
         paper = PAPER_CUBE_FD_S.get(p, {}).get(E)
         log(f"cube h^-1={E} p={p} n={ctx.n[0]} N={ctx.N}: setup {t_setup:.2f} s; apply " +

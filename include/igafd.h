@@ -49,8 +49,14 @@ typedef enum {
   IGAFD_ERR_BREAKDOWN = -6     /* CG breakdown: p^T A p <= 0 or not finite         */
 } igafd_status;
 
-/* precision of the mode products inside the preconditioner apply */
-typedef enum { IGAFD_FP64 = 0, IGAFD_FP32 = 1, IGAFD_BF16 = 2 } igafd_precision;
+/* precision of the mode products inside the preconditioner apply.
+ * IGAFD_BF16X3: split BF16 (Henry, Tang and Heinecke, "Leveraging the bfloat16
+ * artificial intelligence datatype for higher-precision computations", 2019):
+ * each FP32 operand x is held as hi + lo with hi = bf16(x), lo = bf16(x - hi),
+ * and a product a b is taken as lo_a hi_b + hi_a lo_b + hi_a hi_b (three BF16
+ * MFMAs, FP32 accumulation): about 2^-16 relative error per product instead of
+ * BF16's 2^-9, on the same BF16 matrix cores. */
+typedef enum { IGAFD_FP64 = 0, IGAFD_FP32 = 1, IGAFD_BF16 = 2, IGAFD_BF16X3 = 3 } igafd_precision;
 
 /* geometry maps F (analytic, evaluated exactly at the quadrature points) */
 enum {
@@ -127,7 +133,7 @@ igafd_status igafd_load_vector(igafd_ctx* ctx, int rhs_kind, double* b_dev);
 igafd_status igafd_apply_A(igafd_ctx* ctx, const double* x_dev, double* y_dev);
 
 /* s = P^-1 r by fast diagonalisation (Alg. 1 / Alg. 3), mode products in the
- * given precision (FP64, FP32, or BF16 inputs with FP32 accumulation); r and s
+ * given precision (FP64, FP32, BF16 inputs with FP32 accumulation, or split BF16); r and s
  * stay FP64.  With a scaling set (igafd_set_scaling) computes S P^-1 S r.
  * r_dev, s_dev: N doubles; s may not alias r. */
 igafd_status igafd_apply_precond(igafd_ctx* ctx, int precision, const double* r_dev, double* s_dev);

@@ -18,8 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigafd.so")
 
 IGAFD_OK, IGAFD_NOT_CONVERGED = 0, 1
-IGAFD_FP64, IGAFD_FP32, IGAFD_BF16 = 0, 1, 2
-PRECISIONS = {"fp64": IGAFD_FP64, "fp32": IGAFD_FP32, "bf16": IGAFD_BF16}
+IGAFD_FP64, IGAFD_FP32, IGAFD_BF16, IGAFD_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": IGAFD_FP64, "fp32": IGAFD_FP32, "bf16": IGAFD_BF16, "bf16x3": IGAFD_BF16X3}
 GEOM_KINDS = {"identity": 0, "ring": 1, "warped": 2}
 COEF_KINDS = {"one": 0, "sincos": 1}
 RHS_KINDS = {"sinprod": 0, "paper_poly": 1, "bubble": 2, "one": 3}

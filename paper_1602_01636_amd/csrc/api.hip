@@ -455,7 +455,7 @@ igafd_status check_opts(const igafd_ctx* c, const igafd_solve_opts* o) {
     set_error("FP32/BF16 preconditioner applies need the flexible CG form");
     return IGAFD_ERR_ARG;
   }
-  if (o->precision < IGAFD_FP64 || o->precision > IGAFD_BF16) {
+  if (o->precision < IGAFD_FP64 || o->precision > IGAFD_BF16X3) {
     set_error("unknown precision");
     return IGAFD_ERR_ARG;
   }

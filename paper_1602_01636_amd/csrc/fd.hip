@@ -17,8 +17,10 @@
 // matrices Wm (at most npad x npad, zero padded) stay in L1/L2.
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4),
-// BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x16_bf16).  r and s are
-// FP64; intermediates are FP64 for FP64 and FP32 otherwise.
+// BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x16_bf16), and split
+// BF16 (each FP32 operand as hi + lo BF16 parts, three BF16 MFMAs per
+// product).  r and s are FP64; intermediates are FP64 for FP64 and FP32
+// otherwise.
 //
 // Fused epilogues: scaling by the eigenvalue sums, the diagonal S of the
 // scaled preconditioner S P^-1 S on input and output, and the partial sums of
@@ -41,6 +43,24 @@ __device__ inline short to_bf16(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
   return (short)(u >> 16);
 }
+__device__ inline float from_bf16(short h) { return __uint_as_float((unsigned)(unsigned short)h << 16); }
+
+// Split BF16 (Henry, Tang and Heinecke, 2019): x = hi + lo + e with
+// hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32), |e| <= 2^-18 |x|.
+__device__ inline void split4(const float* x, s4_t& hi, s4_t& lo) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hi[j] = to_bf16(x[j]);
+    lo[j] = to_bf16(x[j] - from_bf16(hi[j]));
+  }
+}
+// a b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b (the lo_a lo_b term, <= 2^-18 |a b|,
+// is dropped); the small terms go first into the FP32 accumulator
+__device__ inline f4_t mma_bf16x3(const s4_t& ahi, const s4_t& alo, const s4_t& bhi, const s4_t& blo, f4_t c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+}
 
 // Operand layouts (checked on gfx950): A lane l holds row l%16, B lane l holds
 // column l%16, both with contracted index KPL*(l/16) + j.  Result register r
@@ -52,6 +72,8 @@ struct PF64 {
   static constexpr int KS = 4;
   static constexpr int KPL = 1;  // contracted-index values per lane per K-step
   static constexpr bool ROW_STRIDE4 = true;
+  static constexpr bool SPLIT = false;
+  static constexpr int ID = IGAFD_FP64;
 };
 struct PF32 {
   using W = float;
@@ -59,6 +81,8 @@ struct PF32 {
   static constexpr int KS = 4;
   static constexpr int KPL = 1;
   static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool SPLIT = false;
+  static constexpr int ID = IGAFD_FP32;
 };
 struct PBF16 {
   using W = short;
@@ -66,6 +90,18 @@ struct PBF16 {
   static constexpr int KS = 16;
   static constexpr int KPL = 4;
   static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool SPLIT = false;
+  static constexpr int ID = IGAFD_BF16;
+};
+// split BF16: the matrices are read in FP32 and split per lane like the data
+struct PBF16X3 {
+  using W = float;
+  using acc = f4_t;
+  static constexpr int KS = 16;
+  static constexpr int KPL = 4;
+  static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool SPLIT = true;
+  static constexpr int ID = IGAFD_BF16X3;
 };
 
 enum { EPI_LAMBDA = 1, EPI_PRESCALE = 2, EPI_POSTSCALE = 4, EPI_DOT = 8 };
@@ -100,6 +136,13 @@ __device__ inline f4_t mfma<PBF16>(const short* a, const float* bf, const double
   s4_t av = {a[0], a[1], a[2], a[3]};
   s4_t bv = {to_bf16(bf[0]), to_bf16(bf[1]), to_bf16(bf[2]), to_bf16(bf[3])};
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+}
+template <>
+__device__ inline f4_t mfma<PBF16X3>(const float* a, const float* bf, const double*, f4_t c) {
+  s4_t ahi, alo, bhi, blo;
+  split4(a, ahi, alo);
+  split4(bf, bhi, blo);
+  return mma_bf16x3(ahi, alo, bhi, blo, c);
 }
 
 // D[k][c] = sum_i Wm[k][i] X(i, c) for k in this block's row range and the
@@ -279,6 +322,11 @@ struct Grp<PBF16> {
   using V = float;
   static constexpr int G = 2;
 };
+template <>
+struct Grp<PBF16X3> {
+  using V = float;
+  static constexpr int G = 2;
+};
 
 typedef double d2u_t __attribute__((ext_vector_type(2), aligned(8)));
 typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
@@ -412,6 +460,18 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
           if (wave + kFusedWaves * m < mtiles) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) grp_mma<Pr>(a[u][m], b[u][t], acc[m][t]);
+          }
+      } else if constexpr (Pr::SPLIT) {
+        s4_t pa[MT], la[MT], pb[NT], lb[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) split4(a[u][m], pa[m], la[m]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) split4(b[u][t], pb[t], lb[t]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (wave + kFusedWaves * m < mtiles) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mma_bf16x3(pa[m], la[m], pb[t], lb[t], acc[m][t]);
           }
       } else {
         s4_t pa[MT], pb[NT];
@@ -693,6 +753,8 @@ template <>
 const float* wmat<PF32>(const DevDir& d, int which) { return d.W32[which]; }
 template <>
 const short* wmat<PBF16>(const DevDir& d, int which) { return reinterpret_cast<const short*>(d.Wbf[which]); }
+template <>
+const float* wmat<PBF16X3>(const DevDir& d, int which) { return d.W32[which]; }
 
 int dot_blocks_for(const igafd_ctx* c) {
   const ModeShape ms = mode_shape(c->n[0], c->fd_tiles);
@@ -700,8 +762,8 @@ int dot_blocks_for(const igafd_ctx* c) {
   return grid_x(C, 1, ms.nblk);
 }
 
-// Applies with long directions use the tiled products of gemm.hip (FP64, FP32
-// and BF16 operands): 2D grids with n1 + n2 >= 384, 3D tensors with a direction
+// Applies with long directions use the tiled products of gemm.hip (in every
+// precision): 2D grids with n1 + n2 >= 384, 3D tensors with a direction
 // longer than the fused passes take.  IGAFD_FD_GEMM=0/1 at setup forces the
 // choice.
 constexpr int kGemmAutoN = 384;
@@ -752,7 +814,7 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
     return stt;
   if (c->dim == 3) {
     {
-      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
+      const int prec = Pr::ID;
       if (use_gemm(c, prec)) return fd_apply_gemm3d(c, prec, r, s, S, partial, flag);
     }
     // forward: direction 1 (fast axis), 2, 3 (+ eigenvalue scaling)
@@ -768,7 +830,7 @@ igafd_status apply(igafd_ctx* c, const double* r, double* s, const double* S, do
     IGAFD_TRY((launch_mode<Pr, true, T, double>(st, c->fd_tiles, b0, s, wmat<Pr>(d[0], 1), d[0].npad, n1, n2 * n3, 1, 0, e_out)));
   } else {
     {
-      const int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
+      const int prec = Pr::ID;
       if (use_gemm(c, prec)) return fd_apply_gemm2d(c, prec, r, s, S, partial, flag, ldr, lds);
     }
     IGAFD_TRY((launch_mode<Pr, true, double, T>(st, c->fd_tiles, r, b0, wmat<Pr>(d[0], 0), d[0].npad, n1, n2, 1, 0, e_in,
@@ -833,7 +895,7 @@ igafd_status schwarz(igafd_ctx* c, const double* r, double* s, double* partial, 
   }
   s1->fd_tiles = s2->fd_tiles = c->fd_tiles;
   igafd_status st;
-  constexpr int prec = std::is_same<Pr, PF64>::value ? IGAFD_FP64 : std::is_same<Pr, PF32>::value ? IGAFD_FP32 : IGAFD_BF16;
+  constexpr int prec = Pr::ID;
   if (use_gemm(s1, prec) && use_gemm(s2, prec)) {
     // both subdomain applies by tiled products, each pass of the two in one launch
     st = fd_apply_gemm2d_pair(prec, s2, r, n, s, n, s1, r, n, c->fdbuf[0], h, flag);
@@ -861,6 +923,8 @@ igafd_status schwarz_apply(igafd_ctx* c, int prec, const double* r, double* s, c
       return schwarz<PF32, float>(c, r, s, partial, flag);
     case IGAFD_BF16:
       return schwarz<PBF16, float>(c, r, s, partial, flag);
+    case IGAFD_BF16X3:
+      return schwarz<PBF16X3, float>(c, r, s, partial, flag);
     default:
       set_error("unknown precision");
       return IGAFD_ERR_ARG;
@@ -902,11 +966,13 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
         return apply_fused<PF64, double, double>(c, Wf, Wb, r, s, S, partial, flag);
       }
       case IGAFD_FP32:
-      case IGAFD_BF16: {
+      case IGAFD_BF16:
+      case IGAFD_BF16X3: {
         const float* Wf[3] = {d[0].W32[0], d[1].W32[0], d[2].W32[0]};
         const float* Wb[3] = {d[0].W32[1], d[1].W32[1], d[2].W32[1]};
-        return prec == IGAFD_FP32 ? apply_fused<PF32, float, float>(c, Wf, Wb, r, s, S, partial, flag)
-                                  : apply_fused<PBF16, float, float>(c, Wf, Wb, r, s, S, partial, flag);
+        if (prec == IGAFD_FP32) return apply_fused<PF32, float, float>(c, Wf, Wb, r, s, S, partial, flag);
+        if (prec == IGAFD_BF16) return apply_fused<PBF16, float, float>(c, Wf, Wb, r, s, S, partial, flag);
+        return apply_fused<PBF16X3, float, float>(c, Wf, Wb, r, s, S, partial, flag);
       }
       default:
         break;
@@ -919,6 +985,8 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
       return apply<PF32, float>(c, r, s, S, partial, flag);
     case IGAFD_BF16:
       return apply<PBF16, float>(c, r, s, S, partial, flag);
+    case IGAFD_BF16X3:
+      return apply<PBF16X3, float>(c, r, s, S, partial, flag);
     default:
       set_error("unknown precision");
       return IGAFD_ERR_ARG;

@@ -43,12 +43,14 @@ struct G64 {
   using acc = gd4_t;
   static constexpr bool ROW_STRIDE4 = true;
   static constexpr bool BF16 = false;
+  static constexpr bool SPLIT = false;
 };
 struct G32 {
   using V = float;
   using acc = gf4_t;
   static constexpr bool ROW_STRIDE4 = false;
   static constexpr bool BF16 = false;
+  static constexpr bool SPLIT = false;
 };
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x16_bf16): the slices are
 // staged in FP32 as for G32; per 16-deep slice each lane rounds four k values
@@ -60,6 +62,17 @@ struct G16 {
   using acc = gf4_t;
   static constexpr bool ROW_STRIDE4 = false;
   static constexpr bool BF16 = true;
+  static constexpr bool SPLIT = false;
+};
+// Split BF16 (Henry, Tang and Heinecke, 2019): as G16, but each staged FP32
+// value x is split into hi = bf16(x) and lo = bf16(x - hi) and a product is
+// taken as lo_a hi_b + hi_a lo_b + hi_a hi_b (three MFMAs per slice).
+struct G16X3 {
+  using V = float;
+  using acc = gf4_t;
+  static constexpr bool ROW_STRIDE4 = false;
+  static constexpr bool BF16 = true;
+  static constexpr bool SPLIT = true;
 };
 
 typedef short gs4_t __attribute__((ext_vector_type(4)));
@@ -69,6 +82,10 @@ __device__ inline short bf16_bits(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (short)(u >> 16);
+}
+// the low part x - bf16(x) (exact in FP32), rounded to BF16
+__device__ inline short bf16_low(float f, short hi) {
+  return bf16_bits(f - __uint_as_float((unsigned)(unsigned short)hi << 16));
 }
 
 __device__ inline gd4_t mma(double a, double b, gd4_t c) {
@@ -262,7 +279,34 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GProb<TA, TB, TC> p0, GProb<TA,
   auto compute = [&](int buf) {
     const V* as = As + buf * BK * LA;
     const V* bs = Bs + buf * BK * LB;
-    if constexpr (G::BF16) {
+    if constexpr (G::SPLIT) {
+      gs4_t pa[TM], la[TM], pb[TN], lb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = as[(grp + 4 * j) * LA + wm0 + i * 16 + col];
+          pa[i][j] = bf16_bits(v);
+          la[i][j] = bf16_low(v, pa[i][j]);
+        }
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = bs[(grp + 4 * j) * LB + wn0 + t * 16 + col];
+          pb[t][j] = bf16_bits(v);
+          lb[t][j] = bf16_low(v, pb[t][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(la[i], pb[t], acc[i][t], 0, 0, 0);
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[i], lb[t], acc[i][t], 0, 0, 0);
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[i], pb[t], acc[i][t], 0, 0, 0);
+        }
+      return;
+    } else if constexpr (G::BF16) {
       gs4_t pa[TM], pb[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -473,6 +517,8 @@ template <>
 const float* wm<G32>(const DevDir& d, int which) { return d.W32[which]; }
 template <>
 const float* wm<G16>(const DevDir& d, int which) { return d.W32[which]; }
+template <>
+const float* wm<G16X3>(const DevDir& d, int which) { return d.W32[which]; }
 
 // One 2D FD apply (Sec. 4.1 Alg. 1) by four products, or two independent
 // ones (contexts c and c1, same precision) whose four passes share launches.
@@ -614,6 +660,8 @@ igafd_status fd_apply_gemm3d(igafd_ctx* c, int prec, const double* r, double* s,
       return apply3d<G32, float>(c, r, s, S, partial, flag);
     case IGAFD_BF16:
       return apply3d<G16, float>(c, r, s, S, partial, flag);
+    case IGAFD_BF16X3:
+      return apply3d<G16X3, float>(c, r, s, S, partial, flag);
     default:
       set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
@@ -634,6 +682,8 @@ igafd_status fd_apply_gemm2d(igafd_ctx* c, int prec, const double* r, double* s,
       return apply2d<G32, float>(&job, 1, S, partial, flag);
     case IGAFD_BF16:
       return apply2d<G16, float>(&job, 1, S, partial, flag);
+    case IGAFD_BF16X3:
+      return apply2d<G16X3, float>(&job, 1, S, partial, flag);
     default:
       set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
@@ -654,6 +704,8 @@ igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int
       return apply2d<G32, float>(jobs, 2, nullptr, nullptr, flag);
     case IGAFD_BF16:
       return apply2d<G16, float>(jobs, 2, nullptr, nullptr, flag);
+    case IGAFD_BF16X3:
+      return apply2d<G16X3, float>(jobs, 2, nullptr, nullptr, flag);
     default:
       set_error("internal: unknown precision for the tiled products");
       return IGAFD_ERR_ARG;
