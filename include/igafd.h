@@ -54,8 +54,8 @@ typedef enum {
  * artificial intelligence datatype for higher-precision computations", 2019):
  * each FP32 operand x is held as hi + lo with hi = bf16(x), lo = bf16(x - hi),
  * and a product a b is taken as lo_a hi_b + hi_a lo_b + hi_a hi_b (three BF16
- * MFMAs, FP32 accumulation): about 2^-16 relative error per product instead of
- * BF16's 2^-9, on the same BF16 matrix cores. */
+ * MFMAs, FP32 accumulation): at most about 3 * 2^-16 relative error per product
+ * instead of BF16's 2^-8, on the same BF16 matrix cores. */
 typedef enum { IGAFD_FP64 = 0, IGAFD_FP32 = 1, IGAFD_BF16 = 2, IGAFD_BF16X3 = 3 } igafd_precision;
 
 /* geometry maps F (analytic, evaluated exactly at the quadrature points) */

@@ -46,7 +46,7 @@ __device__ inline short to_bf16(float f) {
 __device__ inline float from_bf16(short h) { return __uint_as_float((unsigned)(unsigned short)h << 16); }
 
 // Split BF16 (Henry, Tang and Heinecke, 2019): x = hi + lo + e with
-// hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32), |e| <= 2^-18 |x|.
+// hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32), |e| <= 2^-16 |x|.
 __device__ inline void split4(const float* x, s4_t& hi, s4_t& lo) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -54,8 +54,9 @@ __device__ inline void split4(const float* x, s4_t& hi, s4_t& lo) {
     lo[j] = to_bf16(x[j] - from_bf16(hi[j]));
   }
 }
-// a b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b (the lo_a lo_b term, <= 2^-18 |a b|,
-// is dropped); the small terms go first into the FP32 accumulator
+// a b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b (the lo_a lo_b term, <= 2^-16 |a b|,
+// is dropped; at most about 3 * 2^-16 |a b| in all); the small terms go first
+// into the FP32 accumulator
 __device__ inline f4_t mma_bf16x3(const s4_t& ahi, const s4_t& alo, const s4_t& bhi, const s4_t& blo, f4_t c) {
   c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);

@@ -6,9 +6,10 @@ small-2D mode products, the scaled apply S P^-1 S and the L-shaped Schwarz
 apply.
 
 Tolerance: the BF16 tests allow 5e-2 for a unit roundoff of 2^-8; the split
-form's error per product is at most about 3 * 2^-18 relative (lo rounded
-to BF16 on each operand, the dropped lo_a lo_b term), 1/340 of that, so the
-same scaling gives 1.5e-4; the tests allow 3e-4.  On every case the split
+form's error per product is at most about 3 * 2^-16 relative (lo rounded
+to BF16 on each operand, the dropped lo_a lo_b term; checked on the host in
+test_split_bf16_bound.py), 3/256 of that, so the same scaling gives 5.9e-4;
+the tests allow 6e-4.  On every case the split
 apply's error must also be at least 30x below the plain BF16 apply's on the
 same input.  Solves use the flexible CG and must match the oracle's FP64
 solution to 1e-7 at rtol 1e-8, like every other precision.
@@ -23,7 +24,7 @@ from oracle import multipatch as mp
 
 pytestmark = pytest.mark.gpu
 
-TOL_X3 = 3e-4
+TOL_X3 = 6e-4
 PROBLEMS = small_problems()
 IDS = [p[0] for p in PROBLEMS]
 

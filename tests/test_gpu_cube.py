@@ -58,13 +58,13 @@ def test_3d_tiled_products(api, name, prob, force, rng, monkeypatch):
         assert api.igafd_get_shape(ctx)["fd_fused"] == 0
         r = rng.standard_normal(ctx.N)
         ref = fd.fd_apply(F, r)
-        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2), ("bf16x3", 3e-4)):
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16", 5e-2), ("bf16x3", 6e-4)):
             s = to_dev(np.full(ctx.N, 3.0))
             api.igafd_apply_precond(ctx, prec, to_dev(r), s)
             assert rel(to_host(s), ref) < tol, prec
         S = np.exp(0.1 * rng.standard_normal(ctx.N))
         api.igafd_set_scaling(ctx, to_dev(S))
-        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16x3", 3e-4)):
+        for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4), ("bf16x3", 6e-4)):
             s = to_dev(np.zeros(ctx.N))
             api.igafd_apply_precond(ctx, prec, to_dev(r), s)
             assert rel(to_host(s), S * fd.fd_apply(F, S * r)) < tol, prec
@@ -133,7 +133,7 @@ def test_precond_only_context(api, rng):
 def test_cube_direct_solver(api, E, p):
     """Unit cube, P = A: the FD apply is the direct solve.  s* drawn, r = P s*
     by the oracle, P^-1 r on the GPU must return s* (FP64, FP32 and split BF16,
-    whose error per product is about 3 * 2^-18 relative)."""
+    whose error per product is at most about 3 * 2^-16 relative)."""
     prob = synth.unit_cube(E, p)
     F = fd.setup(prob)
     n = len(F[0]["lam"])
@@ -147,7 +147,7 @@ def test_cube_direct_solver(api, E, p):
         del r
         s = to_dev(np.zeros(ctx.N))
         for prec, tol in (("fp64", max(1e-11, 2.0 ** -53 * kappa)), ("fp32", max(1e-4, 2.0 ** -24 * kappa)),
-                          ("bf16x3", max(3e-4, 3 * 2.0 ** -18 * kappa))):
+                          ("bf16x3", max(6e-4, 3 * 2.0 ** -16 * kappa))):
             api.igafd_apply_precond(ctx, prec, rd, s)
             err = rel(to_host(s), x)
             print(f"{prec}: rel. error {err:.3g} (tolerance {tol:.3g})", flush=True)
