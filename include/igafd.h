@@ -145,7 +145,7 @@ typedef struct {
   double rtol;                 /* stop when ||r_k||_2 <= rtol ||b||_2 (recursive residual)     */
   int maxit;                   /* maximum CG iterations (0 -> 2000)                            */
   int precision;               /* igafd_precision of the preconditioner apply                  */
-  int flexible;                /* 1: Polak-Ribiere beta (required for FP32/BF16 applies)       */
+  int flexible;                /* 1: Polak-Ribiere beta (required for all but FP64 applies)    */
   int use_scaling;             /* 1: S P^-1 S with the scaling set by igafd_set_scaling        */
   int check_every;             /* iterations enqueued between host checks (0 -> 4)             */
   int use_x0;                  /* 1: u_dev holds the initial guess; 0: x0 = 0                  */
