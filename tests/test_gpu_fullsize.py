@@ -99,6 +99,9 @@ def test_thick_ring_128_p3(api):
         F = fd.setup(prob)
         check_fd(api, ctx, F, "fp64", 1e-11, 3)
         check_fd(api, ctx, F, "fp32", 1e-4, 3)
+        # split BF16: BF16's 5e-2 scaled by the per-product bounds, 3 * 2^-16 against 2^-8
+        e3 = check_fd(api, ctx, F, "bf16x3", 6e-4, 3)
+        assert e3 * 30 < check_fd(api, ctx, F, "bf16", 5e-2, 3)
         u = to_dev(np.zeros(ctx.N))
         info = api.igafd_solve(ctx, b, u)
         assert info["status"] == "OK" and info["true_relres"] <= 1e-8
@@ -117,7 +120,8 @@ def test_warped_96_p5_bf16(api):
         A_r, b, bg = check_rows(api, ctx, prob, rows, 5)
         F = fd.setup(prob)
         check_fd(api, ctx, F, "fp64", 1e-11, 6)
-        check_fd(api, ctx, F, "bf16", 5e-2, 6)
+        e1 = check_fd(api, ctx, F, "bf16", 5e-2, 6)
+        assert check_fd(api, ctx, F, "bf16x3", 6e-4, 6) * 30 < e1
         u = to_dev(np.zeros(ctx.N))
         info = api.igafd_solve(ctx, b, u, precision="bf16")
         assert info["status"] == "OK" and info["true_relres"] <= 1e-8
