@@ -661,10 +661,13 @@ def run_annulus(args, api, torch, synth):
     ms_per_step = 1e3 * float(np.median(times))
     variants = {}
     if not args.no_variants:
-        ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision="fp32")
-        variants["fp32"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"],
-                            "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
-    kr = kernel_report(api, torch, ctx, reps=20, precisions=("fp64", "fp32"))
+        for prec in ("fp32", "bf16", "bf16x3"):
+            ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, precision=prec)
+            variants[prec] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"],
+                              "true_relres": inf[-1]["true_relres"],
+                              "rel_err_vs_fp64": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))}
+            log(f"{prec}: {variants[prec]}")
+    kr = kernel_report(api, torch, ctx, reps=20)
     iters = infos[-1]["iters"]
     paper = PAPER_ANNULUS.get((E, p))
     log(f"annulus h^-1={E} p={p} N={ctx.N}: setup {t_setup:.2f} s, solve {ms_per_step:.2f} ms, {iters} iterations" +
