@@ -204,15 +204,145 @@ def quadrature_points(problem):
     return np.concatenate(xs), np.concatenate(ws)
 
 
-def q_spectral_bounds(problem):
+def q_spectral_bounds(problem, local=False):
     """Sec. 3 Prop. 1: (qmin, qmax) = the smallest and largest eigenvalue of
     Q = |det J| J^-1 (kappa I) J^-T over the Gauss points of the mesh.  With A
     and P assembled by the same rule, every eigenvalue of P^-1 A lies in
-    [qmin, qmax]."""
+    [qmin, qmax].  local=True also returns qloc, the largest pointwise ratio
+    lambda_max(Q(x)) / lambda_min(Q(x)) over the same points."""
     xi, _ = quadrature_points(problem)
-    lo, hi = np.inf, -np.inf
+    lo, hi, loc = np.inf, -np.inf, 0.0
     for k in range(0, len(xi), 1 << 18):
         Q, _, _ = geometry.q_matrix(problem, xi[k:k + (1 << 18)])
         ev = np.linalg.eigvalsh(Q)
         lo, hi = min(lo, ev[:, 0].min()), max(hi, ev[:, -1].max())
-    return float(lo), float(hi)
+        loc = max(loc, float(np.max(ev[:, -1] / ev[:, 0])))
+    return (float(lo), float(hi), loc) if local else (float(lo), float(hi))
+
+
+def _along(T, B, direction):
+    """Mode product of the (n_d, .., n_1) array T with the matrix B along
+    `direction` (0-based; direction 1 is the last axis): Sec. 2.2 eq. kronprod
+    one factor at a time."""
+    ax = T.ndim - 1 - direction
+    T0 = np.moveaxis(T, ax, 0)
+    Y = (B @ T0.reshape(T0.shape[0], -1)).reshape((B.shape[0],) + T0.shape[1:])
+    return np.moveaxis(Y, 0, ax)
+
+
+def ring_operator(problem, absolute=False):
+    """A of the thick quarter ring (3D) or quarter annulus (2D), K = I, as a
+    matrix-free product x -> A x (flat or shaped (n_d, .., n_1)).
+
+    With J_ij = dF_i/dxi_j, the ring map F = ((1+xi1) cos(pi xi2/2),
+    (1+xi1) sin(pi xi2/2) [, xi3]) has det J = w(xi1) = pi (1 + xi1)/2 and
+    J^T J = diag(1, w^2 [, 1]), so eq. Q gives Q = |det J| (J^T J)^-1 =
+    diag(w, 1/w [, w]): diagonal, each entry a function of xi1 alone.  The
+    tensor Gauss rule of eq. A then factorises into Kronecker products of
+    weighted univariate matrices (direction 1 fastest):
+
+        3D  A = M3 (x) M2 (x) K1[w] + M3 (x) K2 (x) M1[1/w] + K3 (x) M2 (x) M1[w]
+        2D  A = M2 (x) K1[w] + K2 (x) M1[1/w]
+
+    with M[v]_ij = int v B_i B_j and K[v]_ij = int v B_i' B_j' by the same
+    q-point rule.  Each term is applied as mode products with the banded
+    univariate matrices (sparse), so 10^6-10^7 unknowns take a fraction of a
+    second per product.  absolute=True applies the same terms with every
+    univariate entry replaced by its magnitude: an entrywise upper bound of
+    |A|, for row scales sum_j |a_ij| |x_j| of rounding tolerances.  Pinned
+    against assemble_matrix (the element loop)."""
+    import scipy.sparse as sps
+
+    if problem["geometry"]["kind"] != "ring" or problem["coefficient"]["kind"] != "one":
+        raise ValueError("ring_operator needs the ring map and kappa = 1")
+    p, q, d = problem["degree"], problem["quad"], problem["dim"]
+    kn = problem["knots"]
+    w = lambda s: 0.5 * np.pi * (1.0 + s)
+    M1w, K1w = splines.univariate_matrices(kn[0], p, q, weight=w)
+    M1i, _ = splines.univariate_matrices(kn[0], p, q, weight=lambda s: 1.0 / w(s))
+    M2, K2 = splines.univariate_matrices(kn[1], p, q)
+    sp_ = (lambda m: sps.csr_matrix(np.abs(m))) if absolute else sps.csr_matrix
+    if d == 2:
+        terms = [(sp_(K1w), sp_(M2)), (sp_(M1i), sp_(K2))]
+    else:
+        M3, K3 = splines.univariate_matrices(kn[2], p, q)
+        terms = [(sp_(K1w), sp_(M2), sp_(M3)), (sp_(M1i), sp_(K2), sp_(M3)), (sp_(M1w), sp_(M2), sp_(K3))]
+    shape = tuple(t.shape[0] for t in terms[0][::-1])
+
+    def apply(x):
+        flat = np.ndim(x) == 1
+        X = np.asarray(x, float).reshape(shape)
+        out = np.zeros(shape)
+        for term in terms:
+            T = X
+            for direction, B in enumerate(term):
+                T = _along(T, B, direction)
+            out += T
+        return out.reshape(-1) if flat else out
+
+    return apply
+
+
+def _load_tables(problem):
+    """Per direction: composite Gauss points and the weighted basis matrix
+    W_l B_l (points x interior functions)."""
+    p, q = problem["degree"], problem["quad"]
+    xs, Bs = [], []
+    for kn in problem["knots"]:
+        x, w, _ = splines.quadrature(kn, q)
+        xs.append(x)
+        Bs.append(splines.basis(kn, p, x)[:, 1:-1] * w[:, None])
+    return xs, Bs
+
+
+def _load_slabs(problem, f, first, stop, slab):
+    """Contribution to b of the Gauss points whose last-direction index lies
+    in [first, stop), `slab` of them at a time."""
+    d = problem["dim"]
+    xs, Bs = _load_tables(problem)
+    b = np.zeros([B.shape[1] for B in Bs][::-1])
+    for s0 in range(first, stop, slab):
+        sl = slice(s0, min(s0 + slab, stop))
+        grids = np.meshgrid(*([xs[d - 1][sl]] + [xs[l] for l in range(d - 2, -1, -1)]), indexing="ij")
+        pts = np.stack(grids[::-1], axis=-1).reshape(-1, d)  # (direction 1 fastest)
+        x, J = geometry.map_and_jacobian(problem["geometry"], pts)
+        g = (np.abs(np.linalg.det(J)) * geometry.rhs(f, x)).reshape(grids[0].shape)
+        T = g
+        for direction in range(d - 1):
+            T = _along(T, Bs[direction].T, direction)
+        b += _along(T, Bs[d - 1][sl].T, d - 1)
+    return b
+
+
+def assemble_load_tensor(problem, f, slab=4, workers=None, pool_above=1 << 22):
+    """The load vector of assemble_load, b_i = sum_t w_t |det J(t)| f(F(t)) B_i(t),
+    with the sum over the tensor Gauss points taken one direction at a time
+    (sum factorisation; the same sum reordered).  With B_l the matrix of
+    direction l's interior B-splines at its composite Gauss points and W_l
+    its weights, b = (B_d^T W_d (x) .. (x) B_1^T W_1) g for g = |det J| f(F) on
+    the tensor grid of points, visited in slabs of `slab` points along the
+    last direction so that 10^8 points fit in memory.  Grids above
+    `pool_above` points are split over `workers` fresh host processes (numpy holds the
+    interpreter lock in the small-matrix routines, so threads do not scale);
+    their contributions are added in order.  Pinned against assemble_load
+    (the element loop)."""
+    import concurrent.futures
+    import multiprocessing
+    import os
+
+    d = problem["dim"]
+    xs, _ = _load_tables(problem)
+    npts = int(np.prod([len(x) for x in xs]))
+    nlast = len(xs[d - 1])
+    workers = workers or min(16, os.cpu_count() or 1, nlast)
+    if npts <= pool_above or workers <= 1:
+        return _load_slabs(problem, f, 0, nlast, slab).reshape(-1)
+    cuts = np.linspace(0, nlast, workers + 1).astype(int)
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        futs = [pool.submit(_load_slabs, problem, f, int(a), int(b), slab) for a, b in zip(cuts[:-1], cuts[1:])]
+        b = None
+        for fu in futs:
+            part = fu.result()
+            b = part if b is None else b + part
+    return b.reshape(-1)

@@ -84,16 +84,21 @@ def q_matrix(problem, xi):
 
 
 def rhs(f, x):
-    """Right-hand side f(x) of -div(K grad u) = f (Sec. 2.1 eq. poisson)."""
+    """Right-hand side f(x) of -div(K grad u) = f (Sec. 2.1 eq. poisson).
+    Optional keys: "amp" (a factor; for sinprod the whole amplitude, default
+    d pi^2) and, for sinprod, "k" (one frequency per direction, default 1)."""
     kind = f["kind"]
     d = x.shape[1]
-    if kind == "sinprod":        # u = prod sin(pi x_i), K = I
-        return d * np.pi ** 2 * np.prod(np.sin(np.pi * x), axis=1)
+    if kind == "sinprod":        # u = prod sin(pi x_i), K = I (default amp and k)
+        amp = f.get("amp", d * np.pi ** 2)
+        k = np.asarray(f.get("k", np.ones(d)), float)
+        return amp * np.prod(np.sin(k * np.pi * x), axis=1)
+    amp = f.get("amp", 1.0)
     if kind == "paper_poly":     # Sec. 7: f = 2 sum (x_i^2 - x_i)
-        return 2.0 * np.sum(x * x - x, axis=1)
+        return amp * 2.0 * np.sum(x * x - x, axis=1)
     if kind == "bubble":         # u = prod x_l (1 - x_l), K = I
         g = x * (1.0 - x)
-        return 2.0 * sum(np.prod(np.delete(g, i, axis=1), axis=1) for i in range(d))
+        return amp * 2.0 * sum(np.prod(np.delete(g, i, axis=1), axis=1) for i in range(d))
     if kind == "one":
-        return np.ones(len(x))
+        return amp * np.ones(len(x))
     raise ValueError(f"unknown rhs kind {kind!r}")

@@ -42,39 +42,30 @@ def pack(parts):
     return np.concatenate([np.asarray(parts[name], np.float64).reshape(-1) for name, _ in SIZES])
 
 
-def _identity(a):
-    return a
-
-
-def forward(theta, mean, inv_std, feat, rnd=_identity):
-    """Returns t and the activations (h1, h2, normalised inputs).
-
-    `rnd` is applied to the operands of the two matrix products (weights and
-    layer inputs); the identity gives the exact FP64 network, a rounding
-    function models products evaluated on narrower operands."""
+def forward(theta, mean, inv_std, feat):
+    """Returns t and the activations (normalised inputs f, h1, h2)."""
     P = unpack(theta)
     f = (np.asarray(feat, np.float64) - mean) * inv_std
-    h1 = np.tanh(rnd(f) @ rnd(P["W1"]).T + P["b1"])
-    h2 = np.tanh(rnd(h1) @ rnd(P["W2"]).T + P["b2"])
+    h1 = np.tanh(f @ P["W1"].T + P["b1"])
+    h2 = np.tanh(h1 @ P["W2"].T + P["b2"])
     t = h2 @ P["w3"] + P["b3"][0]
     return t, (f, h1, h2)
 
 
-def loss_and_grad(theta, mean, inv_std, feat, target, rnd=_identity):
-    """L = mean (t - target)^2 and dL/dtheta by back-propagation (`rnd` as in
-    forward, applied to the operands of every matrix product)."""
+def loss_and_grad(theta, mean, inv_std, feat, target):
+    """L = mean (t - target)^2 and dL/dtheta by back-propagation."""
     P = unpack(theta)
-    t, (f, h1, h2) = forward(theta, mean, inv_std, feat, rnd)
+    t, (f, h1, h2) = forward(theta, mean, inv_std, feat)
     n = len(t)
     e = t - target
     L = float(np.mean(e * e))
     dt = 2.0 * e / n
     g = {"w3": h2.T @ dt, "b3": np.array([dt.sum()])}
     dz2 = np.outer(dt, P["w3"]) * (1.0 - h2 * h2)
-    g["W2"] = rnd(dz2).T @ rnd(h1)
+    g["W2"] = dz2.T @ h1
     g["b2"] = dz2.sum(axis=0)
-    dz1 = (rnd(dz2) @ rnd(P["W2"])) * (1.0 - h1 * h1)
-    g["W1"] = rnd(dz1).T @ rnd(f)
+    dz1 = (dz2 @ P["W2"]) * (1.0 - h1 * h1)
+    g["W1"] = dz1.T @ f
     g["b1"] = dz1.sum(axis=0)
     return L, pack(g)
 

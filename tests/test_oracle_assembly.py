@@ -221,3 +221,75 @@ def test_sinprod_rhs_converges_to_its_solution(rng):
         errs.append(np.abs(_evaluate(prob, u, pts) - np.prod(np.sin(np.pi * pts), axis=1)).max())
     assert errs[0] < 1e-4
     assert errs[0] / errs[1] > 10  # order p+1 = 4 convergence
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 2), (3, 3)])
+def test_ring_operator_equals_element_assembly(dim, p, rng):
+    """The matrix-free Kronecker form of the ring's A (used at the full
+    workload size) against the element loop, with a different knot vector
+    in every direction; the absolute form bounds |A| entrywise."""
+    Es = [4, 3, 5][:dim]
+    kn = [synth.jittered_knots(E, p, 20 + E) for E in Es]
+    prob = synth.make_problem(dim, p, kn, geometry={"kind": "ring"})
+    A = assembly.assemble_matrix(prob)
+    op = assembly.ring_operator(prob)
+    aop = assembly.ring_operator(prob, absolute=True)
+    x = rng.standard_normal(A.shape[0])
+    np.testing.assert_allclose(op(x), A @ x, atol=1e-14 * (abs(A) @ np.abs(x)).max())
+    # entrywise: column j of each operator
+    eye = np.eye(A.shape[0])
+    Ad = A.toarray()
+    cols = np.stack([op(eye[j]) for j in range(A.shape[0])], axis=1)
+    np.testing.assert_allclose(cols, Ad, atol=1e-14 * np.abs(Ad).max())
+    acols = np.stack([aop(eye[j]) for j in range(A.shape[0])], axis=1)
+    assert np.all(acols >= np.abs(Ad) - 1e-14 * np.abs(Ad).max())
+    with pytest.raises(ValueError):
+        assembly.ring_operator(synth.uniform_problem(dim, Es, p))
+
+
+@pytest.mark.parametrize("dim,geom", [(2, {"kind": "ring"}), (3, {"kind": "ring"}), (3, "warped"), (3, None)])
+def test_tensor_load_vector_equals_element_loop(dim, geom):
+    """The sum-factorised load vector (used at the full workload size)
+    against the element loop, in one process and over a pool of processes."""
+    p = 3
+    g = synth.warped_geometry(3, dim=dim) if geom == "warped" else geom
+    kn = [synth.jittered_knots(E, p, 30 + E) for E in [5, 4, 6][:dim]]
+    prob = synth.make_problem(dim, p, kn, geometry=g)
+    for f in (synth.RHS_SINPROD, synth.RHS_PAPER_POLY, {"kind": "sinprod", "amp": 2.5, "k": [2, 1, 3][:dim]}):
+        ref = assembly.assemble_load(prob, f)
+        b = assembly.assemble_load_tensor(prob, f, slab=2)
+        np.testing.assert_allclose(b, ref, atol=1e-15 * np.abs(ref).max() * 10)
+    b2 = assembly.assemble_load_tensor(prob, synth.RHS_SINPROD, slab=3, workers=2, pool_above=0)
+    np.testing.assert_allclose(b2, assembly.assemble_load(prob, synth.RHS_SINPROD),
+                               atol=1e-14 * np.abs(b2).max())
+
+
+def test_sinprod_parameters_closed_form():
+    """f = a sin(k1 pi x) sin(k2 pi y) on the unit square is separable, so its
+    load vector is a times the Kronecker product of two 1D integrals
+    int sin(k pi s) B_i(s) ds (scipy basis, 12-point Gauss rule per element)."""
+    p = 2
+    kn = [synth.jittered_knots(6, p, 41), synth.jittered_knots(5, p, 42)]
+    prob = synth.make_problem(2, p, kn, quad=10)
+    f = {"kind": "sinprod", "amp": 1.7, "k": [3, 2]}
+    b = assembly.assemble_load(prob, f)
+
+    def one_d(knots, k):
+        xs, ws = [], []
+        kk = np.asarray(knots)
+        for i in range(len(kk) - 1):
+            if kk[i] < kk[i + 1]:
+                t, w = np.polynomial.legendre.leggauss(12)
+                xs.append(kk[i] + (kk[i + 1] - kk[i]) * (t + 1) / 2)
+                ws.append(w * (kk[i + 1] - kk[i]) / 2)
+        x, w = np.concatenate(xs), np.concatenate(ws)
+        return scipy_basis(kk, p, x)[:, 1:-1].T @ (w * np.sin(k * np.pi * x))
+
+    ref = 1.7 * np.kron(one_d(kn[1], 2), one_d(kn[0], 3))
+    # 10 and 12 Gauss points per element: both rules are accurate to roundoff
+    np.testing.assert_allclose(b, ref, atol=1e-13 * np.abs(ref).max())
+    # the frequencies matter: k = (2, 3) is a different vector
+    other = assembly.assemble_load(prob, {"kind": "sinprod", "amp": 1.7, "k": [2, 3]})
+    assert np.abs(other - ref).max() > 1e-2 * np.abs(ref).max()
+    b_def = assembly.assemble_load(prob, {"kind": "sinprod", "amp": 2 * np.pi ** 2, "k": [1, 1]})
+    np.testing.assert_allclose(b_def, assembly.assemble_load(prob, synth.RHS_SINPROD), rtol=1e-15, atol=0)

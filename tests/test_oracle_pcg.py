@@ -210,3 +210,54 @@ def test_q_spectral_bounds_contain_generalised_eigenvalues():
     assert lo > 0 and ev.min() >= lo * (1 - 1e-12) and ev.max() <= hi * (1 + 1e-12)
     # and the bound is not loose by orders of magnitude
     assert ev.max() / ev.min() > 0.2 * hi / lo
+
+
+def test_q_local_ratio_closed_forms():
+    """qloc = max over the Gauss points of lambda_max(Q) / lambda_min(Q)."""
+    # ring: Q = diag(w, 1/w, w), pointwise ratio w^2, largest at the largest
+    # direction-1 abscissa, where it equals qmax / qmin
+    E, p = 5, 2
+    prob = synth.uniform_problem(3, [E, 3, 4], p, geometry={"kind": "ring"})
+    g, _ = np.polynomial.legendre.leggauss(p + 1)
+    w = np.pi * (1.0 + ((np.arange(E)[:, None] + 0.5 * (g[None, :] + 1.0)) / E).ravel()) / 2.0
+    lo, hi, loc = assembly.q_spectral_bounds(prob, local=True)
+    assert abs(loc - (w.max() ** 2)) < 1e-12 and abs(loc - hi / lo) < 1e-12
+    # identity map with a coefficient: Q = kappa I, isotropic at every point
+    prob = synth.uniform_problem(3, 4, 2, coefficient=synth.sincos_coefficient(0.5, 1, 1, 0.0, 0.0))
+    lo, hi, loc = assembly.q_spectral_bounds(prob, local=True)
+    assert abs(loc - 1.0) < 1e-12 and hi / lo > 2.0
+    # 2D warped map: the ratio of a 2x2 SPD matrix from its trace and determinant
+    prob = synth.uniform_problem(2, [6, 5], 3, geometry=synth.warped_geometry(4, dim=2),
+                                 coefficient=synth.sincos_coefficient(0.3, 2, 1, 0.5, 0.1))
+    xi, _ = assembly.quadrature_points(prob)
+    from oracle import geometry
+    Q, _, _ = geometry.q_matrix(prob, xi)
+    t = Q[:, 0, 0] + Q[:, 1, 1]
+    det = Q[:, 0, 0] * Q[:, 1, 1] - Q[:, 0, 1] ** 2
+    disc = np.sqrt(t * t - 4 * det)
+    ratio = (t + disc) / (t - disc)
+    lo, hi, loc = assembly.q_spectral_bounds(prob, local=True)
+    assert abs(loc - ratio.max()) < 1e-10 * ratio.max()
+    assert 1.0 < loc <= hi / lo
+
+
+def test_scaling_gate_rule_on_the_oracle():
+    """The rule behind the library's scaling gate, checked on the oracle: where
+    Q is anisotropic but of constant size (ring: (qmax/qmin) / qloc = 1) the
+    diagonal scaling S P^-1 S costs iterations; where its size varies
+    (constant map, kappa varying 3x: ratio 3) it saves many."""
+    from oracle import mlp as omlp
+    for prob, gate in ((synth.thick_ring(E=12, p=3), False),
+                       (synth.uniform_problem(3, 12, 3, coefficient=synth.sincos_coefficient(0.5, 1, 1, 0, 0)), True)):
+        lo, hi, loc = assembly.q_spectral_bounds(prob, local=True)
+        assert ((hi / lo) / loc >= 2.0) == gate
+        A = assembly.assemble_matrix(prob)
+        F = fd.setup(prob)
+        b = assembly.assemble_load(prob, synth.RHS_SINPROD)
+        S = np.exp(omlp.targets(prob, A))
+        _, i0 = pcg.solve(prob, A, F, b)
+        _, i1 = pcg.solve(prob, A, F, b, scaling=S)
+        if gate:
+            assert i1["iters"] <= 0.7 * i0["iters"]
+        else:
+            assert i1["iters"] >= i0["iters"]
