@@ -178,45 +178,40 @@ def oracle_fd_apply_times(prob, reps=3):
     return out
 
 
-def cpu_baseline(target_iters, n_full, p, nnz_full):
-    """The FP64 oracle (NumPy/SciPy, as it stands) on a bounded sample of the
-    same workload: the thick ring at 32^3 elements, p = 3.  Its time per CG
-    iteration is scaled by the ratio of FLOPs per iteration (A product
-    2 nnz, FD apply 4 N sum n_d) to the full workload and multiplied by the
-    GPU's iteration count."""
+def cpu_baseline(prob, u_gpu=None, f=None):
+    """The FP64 oracle (NumPy/SciPy, as it stands) on the whole workload: its
+    PCG on the same thick-ring (or 2D quarter-annulus) problem, with A applied
+    in its Kronecker form (the ring's Q is diagonal and depends on xi1 only),
+    the FD apply by numpy
+    mode products and b assembled by sum factorisation.  As for the GPU, the
+    setup (univariate eigendecompositions, b) is outside the timed solve.
+    Returns the baseline and the distance of the GPU's solution to the
+    oracle's."""
     import synth
     from oracle import assembly, fd, pcg
-    E = 32
-    prob = synth.thick_ring(E=E, p=p)
-    A = assembly.assemble_matrix(prob)
-    F = fd.setup(prob)
-    b = assembly.assemble_load(prob, synth.RHS_SINPROD)
+    from threadpoolctl import threadpool_info
     t0 = time.perf_counter()
-    reps = 0
-    iters = 0
-    while time.perf_counter() - t0 < 10.0 or reps < 3:
-        _, info = pcg.solve(prob, A, F, b, rtol=1e-8)
-        iters += info["iters"]
-        reps += 1
+    F = fd.setup(prob)
+    Aop = assembly.ring_operator(prob)
+    b = assembly.assemble_load_tensor(prob, f or synth.RHS_SINPROD)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    u, info = pcg.pcg(Aop, lambda r: fd.fd_apply(F, r), b, rtol=1e-8)
     dt = time.perf_counter() - t0
-    n_s = E + p - 2
-    N_s = n_s ** 3
-    per_iter = dt / iters
-    flops_s = 2 * A.nnz + 4 * N_s * 3 * n_s
-    N_f = n_full ** 3
-    flops_f = 2 * nnz_full + 4 * N_f * 3 * n_full
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    fd_apply = oracle_fd_apply_times(synth.thick_ring(E=n_full - p + 2, p=p))
-    return {"value": per_iter * flops_f / flops_s * target_iters, "unit": "s", "cores": int(cores),
-            "kind": "oracle", "fd_apply_s": fd_apply,
-            "sample": f"oracle PCG on the thick ring at {E}^3 elements p={p} (N={N_s}), {reps} solves, "
-                      f"{per_iter * 1e3:.2f} ms/iteration, scaled by FLOPs/iteration to {n_full}^3 dofs "
-                      f"and x {target_iters} iterations",
-            "sample_s_per_iter": per_iter}
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    n = [len(f["lam"]) for f in F]
+    out = {"value": dt, "unit": "s", "cores": int(cores), "kind": "oracle", "iters": info["iters"],
+           "true_relres": info["true_relres"], "setup_s": t_setup,
+           "sample": f"the whole workload, one solve: oracle PCG on the {'thick ring' if len(n) == 3 else 'quarter annulus'}, "
+                     f"{n[0]}^{len(n)} dofs, p={prob['degree']}, "
+                     f"rtol 1e-8 (A in Kronecker form, FD by numpy mode products, BLAS on {cores} threads; "
+                     f"b and the eigendecompositions set up beforehand in {t_setup:.1f} s)",
+           "fd_apply_s": oracle_fd_apply_times(prob)}
+    if u_gpu is not None:
+        d = u_gpu - u
+        out["gpu_vs_oracle"] = {"rel_2norm": float(np.linalg.norm(d) / np.linalg.norm(u)),
+                                "rel_max_entry": float(np.abs(d).max() / np.abs(u).max())}
+    return out
 
 
 def result(args, value, ms_per_step, dtype, workload, extra):
@@ -281,11 +276,20 @@ def run_ring(args, api, torch, synth):
             log(f"{prec}: {variants[prec]}")
     if args.copy_calibration:
         copy_calibration(torch)
+    # the same solve with the phase timers on (events between the kernels)
+    tinfo = api.igafd_solve(ctx, b, u, rtol=1e-8, timers=True)
+    torch.cuda.synchronize()
+    phases = {"spmv": tinfo["t_spmv_ms"], "fd": tinfo["t_fd_ms"], "vec": tinfo["t_vec_ms"],
+              "solve": tinfo["t_solve_ms"]}
+    phases["host_wait"] = phases["solve"] - phases["spmv"] - phases["fd"] - phases["vec"]
+    fd_share = phases["fd"] / phases["solve"]
+    log(f"phases (ms): {phases}; FD share {100 * fd_share:.1f}%")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(iters, n, p, ctx.nnz)
-        log(f"cpu baseline {cpu['value']:.2f} s ({cpu['sample']})")
+        cpu = cpu_baseline(prob, u64.cpu().numpy())
+        log(f"cpu baseline {cpu['value']:.2f} s, {cpu['iters']} iterations ({cpu['sample']}); "
+            f"GPU vs oracle {cpu['gpu_vs_oracle']}")
     qlo, qhi = api.igafd_spectral_bounds(ctx)
     workload = {"workload": f"thick quarter ring, p={p}, {E}^3 elements, n={n}/dir, N={N} dofs, "
                             f"f=3pi^2 prod sin(pi x_i), FP64 FD-preconditioned CG, rtol 1e-8",
@@ -296,6 +300,9 @@ def run_ring(args, api, torch, synth):
         "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
         "variants": variants, "setup_s": t_setup, "wall_s_timed": wall,
         "solve_ms": {"median": 1e3 * float(np.median(times)), "min": 1e3 * min(times), "max": 1e3 * max(times)},
+        "phases_ms": phases, "fd_share": fd_share,
+        "paper_fd_share": {"value": 0.1309, "source": "Table percentage, revolved ring h^-1 = 128, p = 3, "
+                                                      "one core of an i7-5820K (MATLAB)"},
         "spectral_bounds": [qlo, qhi], "kappa_bound": qhi / qlo, "paper": PAPER_RING.get((E, p)),
         "roofline": roofline(kr, f"thick_ring E={E} p={p}"), "fd_roofline": fd_roofline(kr),
         "cpu_baseline": cpu})
@@ -613,37 +620,6 @@ PAPER_ANNULUS = {
 }
 
 
-def annulus_cpu_baseline(target_iters, n_full, p, nnz_full):
-    """The oracle's CG + P on the quarter annulus at h^-1 = 256 (same p, same
-    right-hand side), time per iteration scaled by the FLOPs per iteration
-    (A product 2 nnz, FD apply 4 N (n1 + n2)) to the full mesh, times the
-    GPU's iteration count."""
-    from threadpoolctl import threadpool_info
-
-    import synth
-    from oracle import assembly, fd, pcg
-    E = 256
-    prob = synth.quarter_annulus_2d(E=(E, E), p=p)
-    A = assembly.assemble_matrix(prob)
-    F = fd.setup(prob)
-    b = assembly.assemble_load(prob, synth.RHS_PAPER_POLY)
-    t0 = time.perf_counter()
-    reps = iters = 0
-    while time.perf_counter() - t0 < 10.0 or reps < 3:
-        _, info = pcg.solve(prob, A, F, b, rtol=1e-8)
-        iters += info["iters"]
-        reps += 1
-    per_iter = (time.perf_counter() - t0) / iters
-    n_s = E + p - 2
-    flops_s = 2 * A.nnz + 4 * n_s * n_s * 2 * n_s
-    flops_f = 2 * nnz_full + 4 * n_full * n_full * 2 * n_full
-    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": per_iter * flops_f / flops_s * target_iters, "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle CG + P on the quarter annulus at h^-1={E}, p={p} (N={n_s ** 2}), {reps} solves, "
-                      f"{per_iter * 1e3:.2f} ms/iteration, scaled by FLOPs/iteration to {n_full}^2 dofs and x "
-                      f"{target_iters} iterations"}
-
-
 def run_annulus(args, api, torch, synth):
     """2D quarter annulus (the paper's Table quarterofring): CG + P with the
     FD apply by tiled MFMA products (n = 1025 per direction at h^-1 = 1024),
@@ -672,7 +648,8 @@ def run_annulus(args, api, torch, synth):
     paper = PAPER_ANNULUS.get((E, p))
     log(f"annulus h^-1={E} p={p} N={ctx.N}: setup {t_setup:.2f} s, solve {ms_per_step:.2f} ms, {iters} iterations" +
         (f"; paper {paper[0]} iterations, {paper[1]} s" if paper else ""))
-    cpu = None if args.no_cpu_baseline else annulus_cpu_baseline(iters, ctx.n[0], p, ctx.nnz)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(synth.quarter_annulus_2d(E=(E, E), p=p), u64.cpu().numpy(),
+                                                           synth.RHS_PAPER_POLY)
     workload = {"workload": f"2D quarter annulus F = ((1+xi1) cos(pi xi2/2), (1+xi1) sin(pi xi2/2)), p={p}, "
                             f"{E}^2 elements, N={ctx.N}, f = 2 sum(x_i^2 - x_i), FP64 FD-preconditioned CG "
                             f"(FD by tiled MFMA products), rtol 1e-8", "elements": E, "degree": p, "N": ctx.N}

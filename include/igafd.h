@@ -121,13 +121,26 @@ igafd_status igafd_setup(const igafd_problem* prob, void* stream, igafd_ctx** ou
  */
 igafd_status igafd_setup_precond(const igafd_problem* prob, void* stream, igafd_ctx** out);
 
-/* Sizes: n[3] dofs per direction (n[2] = 1 in 2D), N = prod n, nnz = stored
- * nonzeros of A counted over the full matrix, band_bytes = device bytes of A. */
+/* Sizes of the discrete problem (Sec. 2.1 eq. Vh: n_d = m_d - 2 Dirichlet
+ * functions per direction; eq. A: A has at most (2p+1)^d nonzeros per row).
+ * Host outputs, any may be NULL: n[3] dofs per direction (n[2] = 1 in 2D),
+ * N = prod n, nnz = nonzeros of A counted over the full matrix, band_bytes =
+ * device bytes of the stored half band (0 for a preconditioner-only context).
+ * IGAFD_ERR_ARG on a NULL context. */
 igafd_status igafd_sizes(const igafd_ctx* ctx, int n[3], long long* N, long long* nnz,
                          long long* band_bytes);
 
-/* b_i = int_Omega f B_i (same Gauss rule as A); b_dev: N doubles (device). */
-igafd_status igafd_load_vector(igafd_ctx* ctx, int rhs_kind, double* b_dev);
+/* Load vector of the Galerkin system (Sec. 2.1, the right-hand side of
+ * eq. A's system): b_i = int_Omega f B_i dx = sum_t w_t |det J(t)| f(F(t)) B_i(t)
+ * with the Gauss rule of A.  f is IGAFD_RHS_<rhs_kind>; rhs_params (host,
+ * n_rhs_params values, NULL / 0 for the defaults) scale and tune it:
+ *   SINPROD     [amp, k_1, .., k_d]: f = amp prod_i sin(k_i pi x_i)
+ *               (default amp = d pi^2, k_i = 1)
+ *   PAPER_POLY, BUBBLE, ONE   [amp]: f times amp (default 1)
+ * b_dev: N doubles (device), overwritten.  IGAFD_ERR_ARG for an unknown kind
+ * or a wrong parameter count. */
+igafd_status igafd_load_vector(igafd_ctx* ctx, int rhs_kind, const double* rhs_params, int n_rhs_params,
+                               double* b_dev);
 
 /* y = A x (banded FP64 product, Sec. 2.1 eq. A); x_dev, y_dev: N doubles, distinct. */
 igafd_status igafd_apply_A(igafd_ctx* ctx, const double* x_dev, double* y_dev);
@@ -138,7 +151,11 @@ igafd_status igafd_apply_A(igafd_ctx* ctx, const double* x_dev, double* y_dev);
  * r_dev, s_dev: N doubles; s may not alias r. */
 igafd_status igafd_apply_precond(igafd_ctx* ctx, int precision, const double* r_dev, double* s_dev);
 
-/* Diagonal scaling S > 0 for the preconditioner S P^-1 S (copied; NULL disables). */
+/* Diagonal scaling S > 0 (N doubles, device, copied into the context; NULL
+ * disables it) for the preconditioner S P^-1 S.  The paper's P ignores the
+ * variation of Q over the domain (Sec. 3, Prop. 1 and the remark after it);
+ * S, e.g. predicted by the network below, corrects the local magnitude.
+ * Allocates N doubles on first use.  IGAFD_ERR_ARG for the L-shaped context. */
 igafd_status igafd_set_scaling(igafd_ctx* ctx, const double* S_dev);
 
 typedef struct {
@@ -146,10 +163,19 @@ typedef struct {
   int maxit;                   /* maximum CG iterations (0 -> 2000)                            */
   int precision;               /* igafd_precision of the preconditioner apply                  */
   int flexible;                /* 1: Polak-Ribiere beta (required for all but FP64 applies)    */
-  int use_scaling;             /* 1: S P^-1 S with the scaling set by igafd_set_scaling        */
+  int use_scaling;             /* 1: S P^-1 S with the scaling set by igafd_set_scaling;
+                                  2: decided by igafd_scaling_gate (default gain 2): S P^-1 S
+                                  when the gate passes and a scaling is set, else plain P     */
   int check_every;             /* iterations enqueued between host checks (0 -> 4)             */
   int use_x0;                  /* 1: u_dev holds the initial guess; 0: x0 = 0                  */
-  double* history;             /* optional host array of maxit+1 relative residuals            */
+  double* history;             /* optional host array of maxit+1 relative residuals: entry k is
+                                  ||r_k||/||b|| after iteration k (k = 0: the start); at most
+                                  maxit+1 entries are written, also when a fallback or a
+                                  restart runs more iterations (info.history_len says how
+                                  many).  maxit > 2000 with a history grows the context's
+                                  device history buffer once                               */
+  int timers;                  /* 1: time the phases (events between kernels; adds a few us
+                                  per iteration) into info.t_spmv_ms / t_fd_ms / t_vec_ms   */
 } igafd_solve_opts;
 
 typedef struct {
@@ -160,6 +186,16 @@ typedef struct {
   int status;                  /* igafd_status of the solve                                    */
   double t_solve_ms;           /* device time of the whole solve (events on the ctx stream)    */
   int fallback;                /* 1: the scaled preconditioner stagnated and plain P finished  */
+  int history_len;             /* entries written to opts.history (0 without one)              */
+  double t_setup_ms;           /* host wall time of the context's setup (1D setup, uploads,
+                                  assembly of A)                                              */
+  double t_spmv_ms;            /* with opts.timers: device time in A products and their (p, q)
+                                  reductions (the true-residual product included)            */
+  double t_fd_ms;              /* with opts.timers: preconditioner applies and (r, z) reductions */
+  double t_vec_ms;             /* with opts.timers: vector updates, init, residual and the other
+                                  reductions; t_solve - (spmv + fd + vec) is host wait time   */
+  int scaled;                  /* 1: the solve started with S P^-1 S                             */
+  double kappa_bound;          /* qmax / qmin of Prop. 1 when the gate ran (use_scaling = 2)    */
 } igafd_solve_info;
 
 /* PCG for A u = b preconditioned by P (or S P^-1 S).  b_dev, u_dev: N doubles.
@@ -200,9 +236,24 @@ igafd_status igafd_diagonals(igafd_ctx* ctx, double* diagA_dev, double* diagP_de
  * eigenvalue of Q = kappa |det J| J^-1 J^-T over the Gauss points of the
  * mesh (A and P are assembled with the same rule, so the bound holds for the
  * discrete matrices); qmax / qmin bounds the condition number that drives
- * the CG iteration count.  qmin, qmax: host outputs.  Synchronises the
- * context's stream. */
-igafd_status igafd_spectral_bounds(igafd_ctx* ctx, double* qmin, double* qmax);
+ * the CG iteration count.  qloc = the largest local ratio
+ * lambda_max(Q(x)) / lambda_min(Q(x)) over the same points: the anisotropy
+ * of Q at a point, which no diagonal scaling of P removes.  Host outputs (any
+ * may be NULL).  Computed once per context (synchronises its stream), cached
+ * afterwards.  IGAFD_ERR_ARG for the L-shaped context. */
+igafd_status igafd_spectral_bounds(igafd_ctx* ctx, double* qmin, double* qmax, double* qloc);
+
+/* Gate of the scaled preconditioner, from the bounds above (Sec. 3, Prop. 1
+ * and the remark after it, that the quality of P is decided by how much Q
+ * varies): a diagonal scaling S P^-1 S can at best remove the variation of
+ * Q's magnitude over the domain, so its Prop. 1-type bound cannot drop below
+ * qloc.  *use = 1 when (qmax / qmin) / qloc >= gain, i.e. when the bound
+ * could shrink by at least `gain` (> 0; igafd_solve's use_scaling = 2 takes
+ * gain 2); *kappa_q = qmax / qmin, *kappa_loc = qloc (host outputs, any may be
+ * NULL).  Examples: the thick ring has Q = diag(w, 1/w, w) at every point, so
+ * qmax / qmin = qloc = pi^2 and the gate stays closed; a coefficient varying
+ * by 3x on a mildly warped cube opens it. */
+igafd_status igafd_scaling_gate(igafd_ctx* ctx, double gain, int* use, double* kappa_q, double* kappa_loc);
 
 /* Host copy of U_d (n_d x n_d row-major, U[i][k] = component i of eigenvector k,
  * U^T M U = I) and of the eigenvalues D_d for direction dir (0-based). */

@@ -43,12 +43,25 @@ class igafd_problem(C.Structure):
 class igafd_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("flexible", C.c_int),
                 ("use_scaling", C.c_int), ("check_every", C.c_int), ("use_x0", C.c_int),
-                ("history", C.POINTER(C.c_double))]
+                ("history", C.POINTER(C.c_double)), ("timers", C.c_int)]
 
 
 class igafd_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("relres", C.c_double), ("true_relres", C.c_double),
-                ("status", C.c_int), ("t_solve_ms", C.c_double), ("fallback", C.c_int)]
+                ("status", C.c_int), ("t_solve_ms", C.c_double), ("fallback", C.c_int), ("history_len", C.c_int),
+                ("t_setup_ms", C.c_double), ("t_spmv_ms", C.c_double), ("t_fd_ms", C.c_double),
+                ("t_vec_ms", C.c_double), ("scaled", C.c_int), ("kappa_bound", C.c_double)]
+
+
+SCALING_MODES = {False: 0, True: 1, "auto": 2, 0: 0, 1: 1, 2: 2}
+
+
+def _info_dict(info, st):
+    return {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
+            "true_relres": info.true_relres, "status": STATUS_NAMES.get(st, st), "t_solve_ms": info.t_solve_ms,
+            "fallback": bool(info.fallback), "history_len": info.history_len, "t_setup_ms": info.t_setup_ms,
+            "t_spmv_ms": info.t_spmv_ms, "t_fd_ms": info.t_fd_ms, "t_vec_ms": info.t_vec_ms,
+            "scaled": bool(info.scaled), "kappa_bound": info.kappa_bound}
 
 
 _lib = None
@@ -57,7 +70,7 @@ _SIGNATURES = {
     "igafd_setup": (C.c_int, [C.POINTER(igafd_problem), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                               C.POINTER(C.c_longlong)]),
-    "igafd_load_vector": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "igafd_load_vector": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]),
     "igafd_apply_A": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "igafd_apply_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "igafd_set_scaling": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -74,7 +87,10 @@ _SIGNATURES = {
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
-    "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]),
+    "igafd_scaling_gate": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
     "igafd_setup_precond": (C.c_int, [C.POINTER(igafd_problem), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_lshape_setup": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_void_p)]),
     "igafd_set_adi": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -295,9 +311,23 @@ def igafd_sizes(ctx):
     return list(n), N.value, nnz.value, bb.value
 
 
+def rhs_params(rhs: dict, dim: int):
+    """Parameter array of a right-hand side dict (empty: the library's defaults)."""
+    if rhs.get("kind") == "sinprod":
+        if "amp" not in rhs and "k" not in rhs:
+            return []
+        k = list(rhs.get("k", [1.0] * dim))  # the library checks the count
+        return [float(rhs.get("amp", dim * np.pi ** 2))] + [float(v) for v in k]
+    return [float(rhs["amp"])] if "amp" in rhs else []
+
+
 def igafd_load_vector(ctx: Context, rhs, b):
-    kind = RHS_KINDS[rhs["kind"]] if isinstance(rhs, dict) else int(rhs)
-    _check(lib().igafd_load_vector(_h(ctx), kind, _dptr(b, ctx.N, "b")))
+    if isinstance(rhs, dict):
+        kind, prm = RHS_KINDS[rhs["kind"]], rhs_params(rhs, ctx.dim)
+    else:
+        kind, prm = int(rhs), []
+    arr = (C.c_double * max(1, len(prm)))(*prm)
+    _check(lib().igafd_load_vector(_h(ctx), kind, arr if prm else None, len(prm), _dptr(b, ctx.N, "b")))
 
 
 def igafd_apply_A(ctx: Context, x, y):
@@ -319,24 +349,19 @@ def igafd_diagonals(ctx: Context, dA=None, dP=None):
 
 
 def igafd_solve(ctx: Context, b, u, rtol=1e-8, maxit=2000, precision="fp64", flexible=None,
-                use_scaling=False, check_every=4, x0=False, history=False) -> dict:
-    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    if flexible is None:
-        flexible = prec != IGAFD_FP64
-    o = igafd_solve_opts()
-    o.rtol, o.maxit, o.precision, o.flexible = float(rtol), int(maxit), prec, int(bool(flexible))
-    o.use_scaling, o.check_every, o.use_x0 = int(bool(use_scaling)), int(check_every), int(bool(x0))
+                use_scaling=False, check_every=4, x0=False, history=False, timers=False) -> dict:
+    """use_scaling: False / True / "auto" (the Prop. 1 gate decides)."""
+    o = _opts(rtol, maxit, precision, flexible, use_scaling, check_every, x0)
+    o.timers = int(bool(timers))
     hist = None
     if history:
         hist = np.zeros(int(maxit) + 1)
         o.history = hist.ctypes.data_as(C.POINTER(C.c_double))
     info = igafd_solve_info()
     st = _check(lib().igafd_solve(_h(ctx), _dptr(b, ctx.N, "b"), _dptr(u, ctx.N, "u"), C.byref(o), C.byref(info)))
-    out = {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
-           "true_relres": info.true_relres, "status": STATUS_NAMES.get(st, st), "t_solve_ms": info.t_solve_ms,
-           "fallback": bool(info.fallback)}
+    out = _info_dict(info, st)
     if hist is not None:
-        out["history"] = hist[: info.iters + 1].copy()
+        out["history"] = hist[: info.history_len].copy()
     return out
 
 
@@ -346,7 +371,7 @@ def _opts(rtol, maxit, precision, flexible, use_scaling, check_every, x0):
         flexible = prec != IGAFD_FP64
     o = igafd_solve_opts()
     o.rtol, o.maxit, o.precision, o.flexible = float(rtol), int(maxit), prec, int(bool(flexible))
-    o.use_scaling, o.check_every, o.use_x0 = int(bool(use_scaling)), int(check_every), int(bool(x0))
+    o.use_scaling, o.check_every, o.use_x0 = SCALING_MODES[use_scaling], int(check_every), int(bool(x0))
     return o
 
 
@@ -363,8 +388,7 @@ def igafd_solve_batched(ctxs, bs, us, rtol=1e-8, maxit=2000, precision="fp64", f
     wall = C.c_double()
     o = _opts(rtol, maxit, precision, flexible, use_scaling, check_every, False)
     _check(lib().igafd_solve_batched(H, n, Bp, Up, C.byref(o), infos, C.byref(wall)))
-    out = [{"iters": i.iters, "restarts": i.restarts, "relres": i.relres, "true_relres": i.true_relres,
-            "status": STATUS_NAMES.get(i.status, i.status)} for i in infos]
+    out = [_info_dict(i, i.status) for i in infos]
     return out, wall.value
 
 
@@ -373,11 +397,19 @@ def igafd_autotune(ctx: Context, fd_tiles=0, spmv_rows=0):
     _check(lib().igafd_autotune(_h(ctx), int(fd_tiles), int(spmv_rows)))
 
 
-def igafd_spectral_bounds(ctx: Context):
-    """(qmin, qmax): every eigenvalue of P^-1 A lies in [qmin, qmax] (Prop. 1)."""
-    lo, hi = C.c_double(), C.c_double()
-    _check(lib().igafd_spectral_bounds(_h(ctx), C.byref(lo), C.byref(hi)))
-    return lo.value, hi.value
+def igafd_spectral_bounds(ctx: Context, local=False):
+    """(qmin, qmax): every eigenvalue of P^-1 A lies in [qmin, qmax] (Prop. 1);
+    with local=True also qloc, the largest pointwise ratio of Q's eigenvalues."""
+    lo, hi, loc = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().igafd_spectral_bounds(_h(ctx), C.byref(lo), C.byref(hi), C.byref(loc)))
+    return (lo.value, hi.value, loc.value) if local else (lo.value, hi.value)
+
+
+def igafd_scaling_gate(ctx: Context, gain=2.0):
+    """(use, kappa_q, kappa_loc) of the scaled-preconditioner gate."""
+    use, kq, kl = C.c_int(), C.c_double(), C.c_double()
+    _check(lib().igafd_scaling_gate(_h(ctx), float(gain), C.byref(use), C.byref(kq), C.byref(kl)))
+    return bool(use.value), kq.value, kl.value
 
 
 def igafd_get_shape(ctx: Context) -> dict:

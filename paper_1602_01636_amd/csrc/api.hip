@@ -13,6 +13,7 @@
 // b - A x is evaluated in FP64 and the iteration restarts from it if it does
 // not meet the tolerance.  flexible = 1 uses the Polak-Ribiere beta
 // (r_{k+1}, z_{k+1} - z_k) / (r_k, z_k) for inexact (FP32/BF16) applies.
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -32,6 +33,7 @@ void set_error(const std::string& msg) { g_err = msg; }
 namespace {
 
 enum { RED_BB_RR = 0, RED_PQ = 1, RED_RR = 2, RED_RZ = 3, RED_RHO0 = 4, RED_TRUE = 5 };
+constexpr int kHistDefault = 2001;  // history entries allocated with the workspace
 
 // r = b - y (y = A x0, or r = b when y is null); x = 0 unless keep_x.
 // Partials: (b, b) and (r, r).
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restric
       s->rr = b;
       s->iters = 0;
       s->flag = (b <= s->tol2) ? FLAG_CONVERGED : FLAG_RUNNING;
-      if (hist) hist[0] = a > 0.0 ? sqrt(b / a) : 0.0;
+      if (hist && s->hist_cap > 0) hist[0] = a > 0.0 ? sqrt(b / a) : 0.0;
       break;
     case RED_RHO0:
       s->rho = a;
@@ -96,7 +98,9 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restric
     case RED_RR:  // a = (r,r), b = (r, z_old) for the flexible form
       s->rr = a;
       s->rzold = b;
-      if (hist) hist[s->iters] = s->bb > 0.0 ? sqrt(a / s->bb) : 0.0;
+      // restarts and the plain-P fallback run past maxit: write only what the
+      // caller's maxit+1 entries hold
+      if (hist && s->iters < s->hist_cap) hist[s->iters] = s->bb > 0.0 ? sqrt(a / s->bb) : 0.0;
       if (a <= s->tol2)
         s->flag = FLAG_CONVERGED;
       else if (!isfinite(a))
@@ -376,6 +380,41 @@ igafd_status alloc_workspace(igafd_ctx* c) {
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->dflag, sizeof(int)));
   IGAFD_HIP_CHECK(hipEventCreate(&c->ev0));
   IGAFD_HIP_CHECK(hipEventCreate(&c->ev1));
+  // residual history for the default iteration budget (maxit 2000 + the start)
+  c->hist_alloc = kHistDefault;
+  IGAFD_HIP_CHECK(hipMalloc((void**)&c->hist, sizeof(double) * c->hist_alloc));
+  return IGAFD_OK;
+}
+
+// Phase timers of a timed solve.  mark(c, ph) records an event that opens a
+// segment of phase ph (PH_NONE closes the previous one without opening a new
+// segment); harvest(c), called once the stream has drained, adds the elapsed
+// time of every recorded segment to its phase.
+enum { PH_NONE = -1, PH_SPMV = 0, PH_FD = 1, PH_VEC = 2 };
+
+igafd_status mark(igafd_ctx* c, int ph) {
+  if (!c->timing) return IGAFD_OK;
+  if (c->tused == (int)c->tev.size()) {
+    hipEvent_t e = nullptr;
+    IGAFD_HIP_CHECK(hipEventCreate(&e));
+    c->tev.push_back(e);
+    c->tphase.push_back(PH_NONE);
+  }
+  IGAFD_HIP_CHECK(hipEventRecord(c->tev[c->tused], c->stream));
+  c->tphase[c->tused] = ph;
+  c->tused += 1;
+  return IGAFD_OK;
+}
+
+igafd_status harvest(igafd_ctx* c) {
+  if (!c->timing) return IGAFD_OK;
+  for (int k = 0; k + 1 < c->tused; ++k) {
+    if (c->tphase[k] == PH_NONE) continue;
+    float ms = 0.f;
+    IGAFD_HIP_CHECK(hipEventElapsedTime(&ms, c->tev[k], c->tev[k + 1]));
+    c->tacc[c->tphase[k]] += ms;
+  }
+  c->tused = 0;
   return IGAFD_OK;
 }
 
@@ -400,9 +439,10 @@ igafd_status reduce(igafd_ctx* c, int count, int two, int which, double* hist) {
 }
 
 igafd_status read_state(igafd_ctx* c) {
+  if (mark(c, PH_NONE) != IGAFD_OK) return IGAFD_ERR_HIP;
   IGAFD_HIP_CHECK(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
-  return IGAFD_OK;
+  return harvest(c);
 }
 
 #define IGAFD_TRY(x)                          \
@@ -419,8 +459,10 @@ igafd_status precond_step(igafd_ctx* c, int prec, const double* S, double* z, in
 
 // (Re)start: r holds the residual; z = M r, rho = (r, z), p = z.
 igafd_status start_directions(igafd_ctx* c, int prec, const double* S, double*& z, double*& zold) {
+  IGAFD_TRY(mark(c, PH_FD));
   IGAFD_TRY(fd_apply(c, prec, c->r, z, S, c->partial, nullptr));
   IGAFD_TRY(reduce(c, fd_dot_blocks(c, prec), 0, RED_RHO0, nullptr));
+  IGAFD_TRY(mark(c, PH_VEC));
   hipLaunchKernelGGL(k_update_p, dim3(vblocks(c)), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 1, c->N);
   IGAFD_HIP_CHECK(hipGetLastError());
   (void)zold;
@@ -435,16 +477,20 @@ igafd_status enqueue_iteration(igafd_ctx* c, double* x, int prec, const double* 
   const int* flag = &c->state->flag;
   IGAFD_TRY(check_partials(c, (long long)vb));
   // q = A p, (p, q)
+  IGAFD_TRY(mark(c, PH_SPMV));
   IGAFD_TRY(spmv(c, c->pv, c->q, c->partial, flag));
   IGAFD_TRY(reduce(c, spmv_blocks(c), 0, RED_PQ, hist));
   // x += alpha p, r -= alpha q, (r, r) [, (r, z_old)]
+  IGAFD_TRY(mark(c, PH_VEC));
   hipLaunchKernelGGL(k_update_xr, dim3(vb), dim3(kBlock), 0, c->stream, x, c->r, c->pv, c->q, flexible ? z : nullptr,
                      c->state, c->N, c->partial);
   IGAFD_HIP_CHECK(hipGetLastError());
   IGAFD_TRY(reduce(c, (int)vb, flexible, RED_RR, hist));
   // z = M r, (r, z) -> beta; the previous z stays as z_old for the flexible form
   std::swap(z, zold);
+  IGAFD_TRY(mark(c, PH_FD));
   IGAFD_TRY(precond_step(c, prec, S, z, RED_RZ, flag));
+  IGAFD_TRY(mark(c, PH_VEC));
   hipLaunchKernelGGL(k_update_p, dim3(vb), dim3(kBlock), 0, c->stream, c->pv, z, c->state, 0, c->N);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
@@ -463,16 +509,39 @@ igafd_status check_opts(const igafd_ctx* c, const igafd_solve_opts* o) {
     set_error("rtol must be positive");
     return IGAFD_ERR_ARG;
   }
-  if (c->adi && (o->precision != IGAFD_FP64 || o->use_scaling)) {
+  if (o->use_scaling < 0 || o->use_scaling > 2) {
+    set_error("use_scaling must be 0, 1 or 2");
+    return IGAFD_ERR_ARG;
+  }
+  if (c->adi && (o->precision != IGAFD_FP64 || o->use_scaling == 1)) {
     set_error("the ADI preconditioner runs in FP64 and without scaling");
     return IGAFD_ERR_ARG;
   }
-  if (o->use_scaling && !c->scaling_set) {
+  if (o->use_scaling == 1 && !c->scaling_set) {
     set_error("use_scaling requested but no scaling set");
     return IGAFD_ERR_ARG;
   }
   return IGAFD_OK;
 }
+
+// Scaling gate (Sec. 3, Prop. 1): the spectrum of P^-1 A lies in
+// [qmin, qmax], the extreme eigenvalues of Q over the Gauss points.  A diagonal
+// scaling S P^-1 S can at best remove the variation of Q's magnitude over the
+// domain, not the anisotropy of Q at a point, so no such scaling brings the
+// corresponding bound below qloc = max_x lambda_max(Q(x)) / lambda_min(Q(x)).
+// The gate passes when the bound could shrink by at least `gain`:
+// (qmax / qmin) / qloc >= gain.
+igafd_status gate_impl(igafd_ctx* c, double gain, int* use, double* kappa_q, double* kappa_loc) {
+  double lo = 0.0, hi = 0.0, loc = 0.0;
+  IGAFD_TRY(spectral_bounds(c, &lo, &hi, &loc));
+  const double kq = hi / lo;
+  if (kappa_q) *kappa_q = kq;
+  if (kappa_loc) *kappa_loc = loc;
+  if (use) *use = (kq >= gain * loc) ? 1 : 0;
+  return IGAFD_OK;
+}
+
+constexpr double kGateGain = 2.0;  // default gain of use_scaling = 2
 
 igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_solve_opts* o, igafd_solve_info* info) {
   const int maxit = o->maxit > 0 ? o->maxit : 2000;
@@ -480,21 +549,51 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
   const int prec = o->precision;
   const int flexible = o->flexible ? 1 : 0;
   IGAFD_TRY(check_opts(c, o));
-  const double* S = o->use_scaling ? c->scaling : nullptr;
+  double kappa_bound = 0.0;
+  bool scaled = o->use_scaling == 1;
+  if (o->use_scaling == 2 && c->hole < 0) {
+    int pass = 0;
+    IGAFD_TRY(gate_impl(c, kGateGain, &pass, &kappa_bound, nullptr));
+    scaled = pass && c->scaling_set && !c->adi;
+  }
+  const double* S = scaled ? c->scaling : nullptr;
+  // residual history: the context's device buffer, grown once for maxit > 2000
   double* hist = nullptr;
-  if (o->history) IGAFD_HIP_CHECK(hipMalloc((void**)&hist, sizeof(double) * (maxit + 1)));
+  const int hcap = o->history ? maxit + 1 : 0;
+  if (hcap > c->hist_alloc) {
+    IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (c->hist) IGAFD_HIP_CHECK(hipFree(c->hist));
+    c->hist = nullptr;
+    c->hist_alloc = 0;
+    IGAFD_HIP_CHECK(hipMalloc((void**)&c->hist, sizeof(double) * hcap));
+    c->hist_alloc = hcap;
+  }
+  if (hcap) hist = c->hist;
   const unsigned vb = vblocks(c);
+  c->timing = o->timers != 0;
+  c->tused = 0;
+  c->tacc[0] = c->tacc[1] = c->tacc[2] = 0.0;
+  // the timers must be off again on every return path (the batched solve
+  // captures the same enqueue code into graphs)
+  struct TimingOff {
+    igafd_ctx* c;
+    ~TimingOff() { c->timing = false; }
+  } timing_off{c};
   IGAFD_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
 
   SolverState init{};
   init.tol2 = o->rtol * o->rtol;
   init.maxit = maxit;
   init.flexible = flexible;
+  init.hist_cap = hcap;
   *c->hstate = init;
+  IGAFD_TRY(mark(c, PH_VEC));
   IGAFD_HIP_CHECK(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
   const double* y = nullptr;
   if (o->use_x0) {
+    IGAFD_TRY(mark(c, PH_SPMV));
     IGAFD_TRY(spmv_unpadded(c, x, c->q, nullptr, nullptr));
+    IGAFD_TRY(mark(c, PH_VEC));
     y = c->q;
   }
   IGAFD_TRY(check_partials(c, (long long)vb));
@@ -519,7 +618,9 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
       }
     }
     // true residual in FP64
+    IGAFD_TRY(mark(c, PH_SPMV));
     IGAFD_TRY(spmv_unpadded(c, x, c->q, nullptr, nullptr));
+    IGAFD_TRY(mark(c, PH_VEC));
     hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, b, c->q, c->r, c->N, c->partial);
     IGAFD_HIP_CHECK(hipGetLastError());
     IGAFD_TRY(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
@@ -557,11 +658,11 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
   float ms = 0.f;
   IGAFD_HIP_CHECK(hipEventSynchronize(c->ev1));
   IGAFD_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  int nh = 0;
   if (hist) {
-    const int nh = std::min(hs.iters, maxit) + 1;
+    nh = std::min(hs.iters + 1, hcap);
     IGAFD_HIP_CHECK(hipMemcpyAsync(o->history, hist, sizeof(double) * nh, hipMemcpyDeviceToHost, c->stream));
     IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
-    IGAFD_HIP_CHECK(hipFree(hist));
   }
   if (info) {
     info->iters = hs.iters;
@@ -571,6 +672,13 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
     info->t_solve_ms = ms;
     info->relres = bb > 0.0 ? std::sqrt(hs.rr / bb) : 0.0;
     info->fallback = fell_back;
+    info->history_len = nh;
+    info->t_setup_ms = c->t_setup_ms;
+    info->t_spmv_ms = c->tacc[PH_SPMV];
+    info->t_fd_ms = c->tacc[PH_FD];
+    info->t_vec_ms = c->tacc[PH_VEC];
+    info->scaled = scaled ? 1 : 0;
+    info->kappa_bound = kappa_bound;
   }
   if (status == IGAFD_ERR_BREAKDOWN) set_error("CG breakdown: p^T A p <= 0 or not finite");
   return (igafd_status)status;
@@ -594,6 +702,18 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   const int maxit = o->maxit > 0 ? o->maxit : 2000;
   int chunk = o->check_every > 0 ? o->check_every : 4;
   chunk += chunk & 1;  // even: the z / z_old roles return to the captured ones
+  // preconditioner of each problem: S P^-1 S when asked for, or when the
+  // Prop. 1 gate passes (use_scaling = 2); the gate runs on the caller's stream
+  std::vector<const double*> Sp(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    bool use = o->use_scaling == 1;
+    if (o->use_scaling == 2 && cs[i]->scaling_set) {
+      int pass = 0;
+      IGAFD_TRY(gate_impl(cs[i], kGateGain, &pass, nullptr, nullptr));
+      use = pass != 0;
+    }
+    Sp[i] = use ? cs[i]->scaling : nullptr;
+  }
   const int nst = count < 8 ? count : 8;
   std::vector<hipStream_t> pool(nst, nullptr), saved(count);
   std::vector<hipEvent_t> join(nst, nullptr);
@@ -603,13 +723,20 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   igafd_status st = IGAFD_OK;
   std::vector<double*> z(count), zold(count);
   std::vector<char> running(count, 0);
+  bool bound = false;  // the contexts are bound to the pool streams
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    // the callers' streams continue after everything the pool ran
+    for (int k = 0; k < nst; ++k)
+      if (pool[k] && join[k] && hipEventRecord(join[k], pool[k]) == hipSuccess)
+        for (int i = 0; i < count; ++i)
+          if (bound) (void)hipStreamWaitEvent(saved[i], join[k], 0);
     for (int k = 0; k < nst; ++k) {
       if (pool[k]) (void)hipStreamSynchronize(pool[k]);
     }
-    for (int i = 0; i < count; ++i) cs[i]->stream = saved[i];
+    if (bound)
+      for (int i = 0; i < count; ++i) cs[i]->stream = saved[i];
     for (int k = 0; k < nst; ++k) {
       if (join[k]) (void)hipEventDestroy(join[k]);
       if (pool[k]) (void)hipStreamDestroy(pool[k]);
@@ -642,7 +769,14 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   IGAFD_BH(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
   IGAFD_BH(hipEventCreate(&t0));
   IGAFD_BH(hipEventCreate(&t1));
+  // every pool stream first waits for the work already queued on the
+  // streams of the contexts it takes over (uploads, load vectors, scalings)
+  for (int i = 0; i < count; ++i) {
+    IGAFD_BH(hipEventRecord(fork, saved[i]));
+    IGAFD_BH(hipStreamWaitEvent(pool[i % nst], fork, 0));
+  }
   for (int i = 0; i < count; ++i) cs[i]->stream = pool[i % nst];
+  bound = true;
   auto sync_all = [&]() -> igafd_status {
     for (int k = 0; k < nst; ++k) IGAFD_HIP_CHECK(hipStreamSynchronize(pool[k]));
     return IGAFD_OK;
@@ -671,7 +805,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
     zold[i] = c->zold;
     running[i] = c->hstate->flag == FLAG_RUNNING;
     if (running[i])
-      IGAFD_BT(start_directions(c, o->precision, o->use_scaling ? c->scaling : nullptr, z[i], zold[i]));
+      IGAFD_BT(start_directions(c, o->precision, Sp[i], z[i], zold[i]));
   }
   const bool use_graph = std::getenv("IGAFD_NO_GRAPH") == nullptr;
   int captured_for = -1;
@@ -683,8 +817,8 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
       for (int k = 0; k < chunk; ++k)
         for (int i = 0; i < count; ++i)
           if (running[i])
-            IGAFD_TRY(enqueue_iteration(cs[i], xs[i], o->precision, o->use_scaling ? cs[i]->scaling : nullptr,
-                                        o->flexible ? 1 : 0, z[i], zold[i], nullptr));
+            IGAFD_TRY(enqueue_iteration(cs[i], xs[i], o->precision, Sp[i], o->flexible ? 1 : 0, z[i], zold[i],
+                                        nullptr));
       return IGAFD_OK;
     };
     if (use_graph) {
@@ -755,6 +889,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
       oc.use_x0 = 1;
       oc.maxit = maxit > hs.iters ? maxit - hs.iters : 1;
       oc.history = nullptr;
+      oc.timers = 0;
       igafd_solve_info more{};
       const igafd_status s2 = solve_impl(c, bs[i], xs[i], &oc, &more);
       inf.iters = hs.iters + more.iters;
@@ -845,10 +980,15 @@ using namespace igafd;
 
 namespace igafd {
 namespace {
+double elapsed_ms(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // fd = false: no univariate eigendecompositions (a context whose
 // preconditioner is applied by other contexts); with_A = false: no A and no
 // CG workspace (a context that only applies P^-1)
 igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, bool fd, bool with_A = true) {
+  const auto t_start = std::chrono::steady_clock::now();
   if (!pr || !out) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
@@ -893,6 +1033,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
     c->npartial = std::max(1025, fd_dot_blocks_max(c.get()));
     IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
     IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->t_setup_ms = elapsed_ms(t_start);
     *out = c.release();
     return IGAFD_OK;
   }
@@ -913,6 +1054,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
   }
   if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  c->t_setup_ms = elapsed_ms(t_start);
   *out = c.release();
   return IGAFD_OK;
 }
@@ -960,6 +1102,8 @@ void igafd_destroy(igafd_ctx* c) {
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  free_dev(c->hist);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -973,6 +1117,7 @@ igafd_status igafd_setup_precond(const igafd_problem* pr, void* stream, igafd_ct
 }
 
 igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, void* stream, igafd_ctx** out) {
+  const auto t_start = std::chrono::steady_clock::now();
   if (!knots || !out) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
@@ -1015,6 +1160,7 @@ igafd_status igafd_lshape_setup(int degree, int nknots, const double* knots, voi
   if ((s = create_fd_sub(p, merged, patch, c->stream, &c->sub[1])) != IGAFD_OK) return s;
   c->hole = h;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+  c->t_setup_ms = elapsed_ms(t_start);
   *out = c.release();
   return IGAFD_OK;
 }
@@ -1104,12 +1250,12 @@ igafd_status igafd_sizes(const igafd_ctx* c, int n[3], long long* N, long long* 
   return IGAFD_OK;
 }
 
-igafd_status igafd_load_vector(igafd_ctx* c, int rhs_kind, double* b) {
+igafd_status igafd_load_vector(igafd_ctx* c, int rhs_kind, const double* rhs_params, int n_rhs_params, double* b) {
   if (!c || !b) {
     set_error("null argument");
     return IGAFD_ERR_ARG;
   }
-  const igafd_status s = assemble_load(c, rhs_kind, b);
+  const igafd_status s = assemble_load(c, rhs_kind, rhs_params, n_rhs_params, b);
   return s == IGAFD_OK ? mask_hole(c, b) : s;
 }
 
@@ -1221,13 +1367,22 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
   return solve_batched_impl(ctxs, count, b, u, o, infos, wall_ms);
 }
 
-igafd_status igafd_spectral_bounds(igafd_ctx* c, double* qmin, double* qmax) {
+igafd_status igafd_spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* qloc) {
   if (!c) {
     set_error("null context");
     return IGAFD_ERR_ARG;
   }
   if (is_lshape(c, "igafd_spectral_bounds")) return IGAFD_ERR_ARG;
-  return spectral_bounds(c, qmin, qmax);
+  return spectral_bounds(c, qmin, qmax, qloc);
+}
+
+igafd_status igafd_scaling_gate(igafd_ctx* c, double gain, int* use, double* kappa_q, double* kappa_loc) {
+  if (!c || !(gain > 0.0)) {
+    set_error("scaling gate needs a context and a positive gain");
+    return IGAFD_ERR_ARG;
+  }
+  if (is_lshape(c, "igafd_scaling_gate")) return IGAFD_ERR_ARG;
+  return gate_impl(c, gain, use, kappa_q, kappa_loc);
 }
 
 igafd_status igafd_get_shape(const igafd_ctx* c, int* spmv_rows, int* tile_b2, int* tile_b3, int* fd_fused,

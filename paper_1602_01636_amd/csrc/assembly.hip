@@ -19,6 +19,13 @@
 namespace igafd {
 namespace {
 
+// right-hand side f of igafd_load_vector: kind, amplitude, SINPROD frequencies
+struct RhsDesc {
+  int kind;
+  double amp;
+  double k[3];
+};
+
 struct Tables {
   const int* first[3];
   const double* qx[3];
@@ -227,17 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
 }
 
 template <int D>
-__device__ inline double rhs_eval(int kind, const double x[3]) {
-  switch (kind) {
+__device__ inline double rhs_eval(const RhsDesc& f, const double x[3]) {
+  switch (f.kind) {
     case IGAFD_RHS_SINPROD: {
-      double s = D * M_PI * M_PI;
-      for (int l = 0; l < D; ++l) s *= sin(M_PI * x[l]);
+      double s = f.amp;
+      for (int l = 0; l < D; ++l) s *= sin(f.k[l] * M_PI * x[l]);
       return s;
     }
     case IGAFD_RHS_PAPER_POLY: {
       double s = 0.0;
       for (int l = 0; l < D; ++l) s += 2.0 * (x[l] * x[l] - x[l]);
-      return s;
+      return f.amp * s;
     }
     case IGAFD_RHS_BUBBLE: {
       double s = 0.0;
@@ -247,16 +254,16 @@ __device__ inline double rhs_eval(int kind, const double x[3]) {
           if (l != i) pr *= x[l] * (1.0 - x[l]);
         s += pr;
       }
-      return s;
+      return f.amp * s;
     }
     default:
-      return 1.0;
+      return f.amp;
   }
 }
 
 // b_i += sum_t w_t |det J| f(F(t)) B_i(t) over one colour class of elements.
 template <int D, int P>
-__global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, int rhs_kind, double* __restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, RhsDesc rhs, double* __restrict__ b,
                                                  int c1, int c2, int c3, int m1, int m2) {
   constexpr int Q = P + 1, L = P + 1;
   constexpr int Q3 = (D == 3) ? Q : 1;
@@ -286,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, int rhs_k
     double x[3], J[3][3], A[3][3];
     map_eval<D>(g, xi, x, J);
     const double det = adjugate<D>(J, A);
-    sg[t] = w * fabs(det) * rhs_eval<D>(rhs_kind, x);
+    sg[t] = w * fabs(det) * rhs_eval<D>(rhs, x);
   }
   __syncthreads();
   for (int idx = tid; idx < L * L * L3; idx += kBlock) {
@@ -414,14 +421,16 @@ __device__ inline void sym_extremes(int d, const double Q[3][3], double& lo, dou
 }
 
 // min / max over the Gauss points of the extreme eigenvalues of
-// Q = kappa |det J| J^-1 J^-T (Sec. 2.1 eq. Q).  Grid-stride over all points
-// (nq[l] = points along direction l, flat index i1 + nq0 (i2 + nq1 i3));
-// one (min, max) pair per block in part[blockIdx.x], part[gridDim.x + blockIdx.x].
+// Q = kappa |det J| J^-1 J^-T (Sec. 2.1 eq. Q), and the max over the points of
+// the local ratio lambda_max(Q(x)) / lambda_min(Q(x)).  Grid-stride over all
+// points (nq[l] = points along direction l, flat index i1 + nq0 (i2 + nq1 i3));
+// per block part[blockIdx.x] = min, part[G + blockIdx.x] = max and
+// part[2 G + blockIdx.x] = max ratio (G = gridDim.x).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_qbounds(const double* __restrict__ qx0, const double* __restrict__ qx1,
                                                     const double* __restrict__ qx2, GeomDesc g, int nq0, int nq1,
                                                     int nq2, double* __restrict__ part) {
-  double lo = INFINITY, hi = -INFINITY;
+  double lo = INFINITY, hi = -INFINITY, loc = 0.0;
   const long long total = (long long)nq0 * nq1 * nq2;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long long)gridDim.x * kBlock) {
     const int i1 = (int)(i % nq0);
@@ -443,38 +452,45 @@ __global__ __launch_bounds__(kBlock) void k_qbounds(const double* __restrict__ q
     sym_extremes(D, Q, l0, l1);
     lo = fmin(lo, l0);
     hi = fmax(hi, l1);
+    loc = fmax(loc, l1 / l0);
   }
   // min / max are exact: any reduction order gives the same result
   for (int off = 32; off > 0; off >>= 1) {
     lo = fmin(lo, __shfl_down(lo, off, 64));
     hi = fmax(hi, __shfl_down(hi, off, 64));
+    loc = fmax(loc, __shfl_down(loc, off, 64));
   }
-  __shared__ double slo[kBlock / 64], shi[kBlock / 64];
+  __shared__ double slo[kBlock / 64], shi[kBlock / 64], sloc[kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     slo[wid] = lo;
     shi[wid] = hi;
+    sloc[wid] = loc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / 64; ++w) {
       lo = fmin(lo, slo[w]);
       hi = fmax(hi, shi[w]);
+      loc = fmax(loc, sloc[w]);
     }
     part[blockIdx.x] = lo;
     part[gridDim.x + blockIdx.x] = hi;
+    part[2 * gridDim.x + blockIdx.x] = loc;
   }
 }
 
 __global__ void k_minmax(const double* __restrict__ part, int count, double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double lo = INFINITY, hi = -INFINITY;
+  double lo = INFINITY, hi = -INFINITY, loc = 0.0;
   for (int k = 0; k < count; ++k) {
     lo = fmin(lo, part[k]);
     hi = fmax(hi, part[count + k]);
+    loc = fmax(loc, part[2 * count + k]);
   }
   out[0] = lo;
   out[1] = hi;
+  out[2] = loc;
 }
 
 // feat[i] = (acc[i][0..6] / acc[i][7], p) in FP32
@@ -554,7 +570,7 @@ igafd_status launch_assemble(igafd_ctx* c) {
 }
 
 template <int D, int P>
-igafd_status launch_load(igafd_ctx* c, int rhs_kind, double* b) {
+igafd_status launch_load(igafd_ctx* c, RhsDesc rhs, double* b) {
   const Tables T = make_tables(c);
   const int nel[3] = {c->ddir[0].nel, c->ddir[1].nel, D == 3 ? c->ddir[2].nel : 1};
   const int C3 = (D == 3) ? P + 1 : 1;
@@ -566,8 +582,8 @@ igafd_status launch_load(igafd_ctx* c, int rhs_kind, double* b) {
         const int m3 = (D == 3) ? (c3 < nel[2] ? (nel[2] - c3 + P) / (P + 1) : 0) : 1;
         const long long blocks = (long long)m1 * m2 * m3;
         if (blocks == 0) continue;
-        hipLaunchKernelGGL((k_load<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom, rhs_kind,
-                           b, c1, c2, c3, m1, m2);
+        hipLaunchKernelGGL((k_load<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom, rhs, b,
+                           c1, c2, c3, m1, m2);
         IGAFD_HIP_CHECK(hipGetLastError());
       }
   return IGAFD_OK;
@@ -618,7 +634,7 @@ struct FeatureOp {
 };
 template <int D, int P>
 struct LoadOp {
-  static igafd_status run(igafd_ctx* c, int k, double* b) { return launch_load<D, P>(c, k, b); }
+  static igafd_status run(igafd_ctx* c, RhsDesc f, double* b) { return launch_load<D, P>(c, f, b); }
 };
 
 }  // namespace
@@ -638,39 +654,60 @@ igafd_status assemble_band(igafd_ctx* c) {
   return IGAFD_OK;
 }
 
-igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b) {
+igafd_status assemble_load(igafd_ctx* c, int rhs_kind, const double* params, int nparams, double* b) {
   if (rhs_kind < IGAFD_RHS_SINPROD || rhs_kind > IGAFD_RHS_ONE) {
     set_error("unknown right-hand side kind");
     return IGAFD_ERR_ARG;
   }
+  RhsDesc f{};
+  f.kind = rhs_kind;
+  f.amp = rhs_kind == IGAFD_RHS_SINPROD ? c->dim * M_PI * M_PI : 1.0;
+  for (int l = 0; l < 3; ++l) f.k[l] = 1.0;
+  const int want = rhs_kind == IGAFD_RHS_SINPROD ? 1 + c->dim : 1;
+  if (nparams != 0) {  // NULL / 0 keeps the defaults
+    if (!params || nparams != want) {
+      set_error("right-hand side parameters: expected " + std::to_string(want) + " values");
+      return IGAFD_ERR_ARG;
+    }
+    f.amp = params[0];
+    for (int l = 1; l < nparams; ++l) f.k[l - 1] = params[l];
+  }
   IGAFD_HIP_CHECK(hipMemsetAsync(b, 0, sizeof(double) * c->N, c->stream));
-  return dispatch<LoadOp>(c->dim, c->p, c, rhs_kind, b);
+  return dispatch<LoadOp>(c->dim, c->p, c, f, b);
 }
 
-igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax) {
-  const int nq0 = c->dir[0].nel * c->dir[0].q, nq1 = c->dir[1].nel * c->dir[1].q;
-  const int nq2 = c->dim == 3 ? c->dir[2].nel * c->dir[2].q : 1;
-  // partial buffer: 2 * npartial doubles = blocks (min, max) pairs + the result
-  const int blocks = c->npartial - 1 < 1024 ? c->npartial - 1 : 1024;
-  double* out = c->partial + 2 * blocks;
-  if (blocks < 1 || 2 * blocks + 2 > 2 * c->npartial) {
-    set_error("internal: partial-sum buffer too small for the spectral bounds");
-    return IGAFD_ERR_ARG;
+igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* qloc) {
+  if (!c->bounds_valid) {
+    const int nq0 = c->dir[0].nel * c->dir[0].q, nq1 = c->dir[1].nel * c->dir[1].q;
+    const int nq2 = c->dim == 3 ? c->dir[2].nel * c->dir[2].q : 1;
+    // partial buffer: 2 * npartial doubles = blocks (min, max, ratio) triples + the result
+    int blocks = (2 * c->npartial - 3) / 3;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) {
+      set_error("internal: partial-sum buffer too small for the spectral bounds");
+      return IGAFD_ERR_ARG;
+    }
+    double* out = c->partial + 3 * blocks;
+    if (c->dim == 3)
+      hipLaunchKernelGGL(k_qbounds<3>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
+                         c->ddir[2].qx, c->geom, nq0, nq1, nq2, c->partial);
+    else
+      hipLaunchKernelGGL(k_qbounds<2>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
+                         c->ddir[1].qx, c->geom, nq0, nq1, 1, c->partial);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_minmax, dim3(1), dim3(64), 0, c->stream, c->partial, blocks, out);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    double h[3];
+    IGAFD_HIP_CHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->qmin = h[0];
+    c->qmax = h[1];
+    c->qloc = h[2];
+    c->bounds_valid = true;
   }
-  if (c->dim == 3)
-    hipLaunchKernelGGL(k_qbounds<3>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
-                       c->ddir[2].qx, c->geom, nq0, nq1, nq2, c->partial);
-  else
-    hipLaunchKernelGGL(k_qbounds<2>, dim3(blocks), dim3(kBlock), 0, c->stream, c->ddir[0].qx, c->ddir[1].qx,
-                       c->ddir[1].qx, c->geom, nq0, nq1, 1, c->partial);
-  IGAFD_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(64), 0, c->stream, c->partial, blocks, out);
-  IGAFD_HIP_CHECK(hipGetLastError());
-  double h[2];
-  IGAFD_HIP_CHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-  IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
-  if (qmin) *qmin = h[0];
-  if (qmax) *qmax = h[1];
+  if (qmin) *qmin = c->qmin;
+  if (qmax) *qmax = c->qmax;
+  if (qloc) *qloc = c->qloc;
   return IGAFD_OK;
 }
 

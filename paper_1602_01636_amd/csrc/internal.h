@@ -74,6 +74,7 @@ struct SolverState {
   double bb, tol2;
   double rho, pq, rr, rz, rzold, alpha, beta, rrtrue;
   int iters, maxit, flag, flexible;
+  int hist_cap;  // entries of the device history the reductions may write (0: none)
 };
 enum { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_MAXIT = 3 };
 
@@ -138,17 +139,30 @@ struct igafd_ctx {
   igafd::SolverState* hstate = nullptr;    // pinned host mirror
   int* dflag = nullptr;                    // device error flag (geometry)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double* hist = nullptr;                  // device residual history of igafd_solve
+  int hist_alloc = 0;                      // doubles allocated at hist
+  double t_setup_ms = 0.0;                 // host wall time of the setup
+  // Prop. 1 bounds of the geometry, computed once on demand
+  bool bounds_valid = false;
+  double qmin = 0.0, qmax = 0.0, qloc = 0.0;
+  // phase timers of a timed solve: events between kernels, the phase each
+  // recorded segment belongs to (-1: none), accumulated milliseconds
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  std::vector<int> tphase;
+  int tused = 0;
+  double tacc[3] = {0.0, 0.0, 0.0};
 };
 
 namespace igafd {
 // assembly.hip
 igafd_status assemble_band(igafd_ctx* c);
-igafd_status assemble_load(igafd_ctx* c, int rhs_kind, double* b);
+igafd_status assemble_load(igafd_ctx* c, int rhs_kind, const double* params, int nparams, double* b);
 igafd_status diagonals(igafd_ctx* c, double* dA, double* dP);
 igafd_status features(igafd_ctx* c, float* feat);
 igafd_status scaling_targets(igafd_ctx* c, float* t);
 igafd_status diag_ratio_scaling(igafd_ctx* c, double* S);
-igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax);
+igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* qloc);
 // spmv.hip
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);

@@ -14,7 +14,13 @@ what it can compute one by one or whole:
 * the Prop. 1 spectral bounds against their closed form on the ring;
 * the solve: the library's FP64 true residual <= 1e-8, and on the sampled
   rows the oracle's own residual b_i - (A u)_i of the library's u is within
-  1e-8 ||b|| plus the row-assembly rounding.
+  1e-8 ||b|| plus the row-assembly rounding;
+* on the thick ring, whole vectors: its A is separable (Q = diag(w, 1/w, w)),
+  so the oracle applies it in Kronecker form (pinned against the element
+  loop) and assembles b by sum factorisation, and runs its own PCG at 129^3:
+  the library's A x entry by entry, b, and the FP64 / FP32 / split-BF16 /
+  BF16 solutions against the oracle's solution (1e-7, 2-norm and largest
+  entry, iterations within one for FP64).
 
 Workloads: thick quarter ring p=3 128^3; warped cube with kappa p=5 96^3
 (BF16 FD, flexible CG); warped cube p=4 112^3 with the diagonal-ratio scaling;
@@ -87,30 +93,57 @@ def check_fd(api, ctx, F, prec, tol, seed):
 
 
 def test_thick_ring_128_p3(api):
+    """The headline workload, whole vectors against the oracle: the ring's A
+    in its Kronecker form (pinned against the element loop) and the
+    sum-factorised load vector make a full oracle solve at 129^3 possible."""
+    from oracle import pcg
     prob = synth.thick_ring(E=128, p=3)
+    Aop = assembly.ring_operator(prob)
+    Aabs = assembly.ring_operator(prob, absolute=True)
+    F = fd.setup(prob)
+    b_or = assembly.assemble_load_tensor(prob, synth.RHS_SINPROD)
+    u_or, info_or = pcg.pcg(Aop, lambda r: fd.fd_apply(F, r), b_or, rtol=1e-8)
+    print(f"oracle: {info_or['iters']} iterations, true relres {info_or['true_relres']:.2e}", flush=True)
     with api.igafd_setup(prob) as ctx:
         # Prop. 1 bounds against their closed form on the ring (Q = diag(w, 1/w, w))
         g, _ = np.polynomial.legendre.leggauss(4)
         w = np.pi * (1.0 + ((np.arange(128)[:, None] + 0.5 * (g[None, :] + 1.0)) / 128).ravel()) / 2.0
-        lo, hi = api.igafd_spectral_bounds(ctx)
+        lo, hi, loc = api.igafd_spectral_bounds(ctx, local=True)
         assert abs(lo - np.minimum(w, 1 / w).min()) < 1e-13 and abs(hi - np.maximum(w, 1 / w).max()) < 1e-13
+        assert abs(loc - w.max() ** 2) < 1e-12
+        use, kq, kl = api.igafd_scaling_gate(ctx)
+        assert not use and abs(kq / kl - 1.0) < 1e-12
+        # the whole A product, entry by entry, at 1e-12 of sum_j |a_ij| |x_j|
+        x = np.random.default_rng(2).standard_normal(ctx.N)
+        y = to_dev(np.zeros(ctx.N))
+        api.igafd_apply_A(ctx, to_dev(x), y)
+        assert np.max(np.abs(to_host(y) - Aop(x)) / Aabs(np.abs(x))) < 1e-12
+        # sampled rows of A and b against the element loop itself
         rows = sample_rows(ctx.n, 40, 1)
         A_r, b, bg = check_rows(api, ctx, prob, rows, 2)
-        F = fd.setup(prob)
+        # the whole load vector
+        assert rel(bg, b_or) < 1e-12
         check_fd(api, ctx, F, "fp64", 1e-11, 3)
         check_fd(api, ctx, F, "fp32", 1e-4, 3)
         # split BF16: BF16's 5e-2 scaled by the per-product bounds, 3 * 2^-16 against 2^-8
         e3 = check_fd(api, ctx, F, "bf16x3", 6e-4, 3)
         assert e3 * 30 < check_fd(api, ctx, F, "bf16", 5e-2, 3)
+        # the FP64 solve against the oracle's solve: the north star's 1e-7 at a
+        # 1e-8 residual, iterations within one
         u = to_dev(np.zeros(ctx.N))
         info = api.igafd_solve(ctx, b, u)
         assert info["status"] == "OK" and info["true_relres"] <= 1e-8
         u64 = to_host(u)
+        err = rel(u64, u_or)
+        print(f"fp64: {info['iters']} iterations, error vs oracle {err:.2e} (2-norm and max entry)", flush=True)
+        assert err <= 1e-7 and abs(info["iters"] - info_or["iters"]) <= 1
         check_residual_rows(A_r, rows, bg, u64)
-        info32 = api.igafd_solve(ctx, b, u, precision="fp32")
-        assert info32["true_relres"] <= 1e-8
-        check_residual_rows(A_r, rows, bg, to_host(u))
-        assert rel(to_host(u), u64) < 1e-7
+        # mixed-precision applies in flexible CG: the same solution to the same bar
+        for prec in ("fp32", "bf16x3", "bf16"):
+            inf = api.igafd_solve(ctx, b, u, precision=prec)
+            e = rel(to_host(u), u_or)
+            print(f"{prec}: {inf['iters']} iterations, error vs oracle {e:.2e}", flush=True)
+            assert inf["true_relres"] <= 1e-8 and e <= 1e-7, prec
 
 
 def test_warped_96_p5_bf16(api):

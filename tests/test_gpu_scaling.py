@@ -1,12 +1,9 @@
 """GPU parity of the learned-scaling pieces against the FP64 oracle:
 features and targets (FP64 device arithmetic stored in FP32 -> 1e-6
-relative); the BF16 network forward and gradients against the FP64 oracle
-whose matrix-product operands are rounded to BF16 exactly where the device
-rounds them, so only FP32 accumulation order (and an occasional one-ulp BF16
-flip after tanhf) differs (1e-3 relative per parameter block; the unrounded FP64 gradient is reported and within 0.1:
-BF16 operands in back-propagation lose up to a few percent to cancellation);
-training (the loss falls, bitwise reproducibly) and the gain of S P^-1 S
-over P."""
+relative); the BF16 network forward and gradients against the exact FP64
+oracle, entry by entry, within a first-order rounding-error bound derived
+below; training (the loss falls, bitwise reproducibly) and the gain of
+S P^-1 S over P."""
 import numpy as np
 import pytest
 
@@ -15,6 +12,9 @@ from helpers import rel, to_dev, to_host
 from oracle import assembly, fd, mlp as omlp, pcg
 
 pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significant bits, round to nearest even)
+U_FP32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -27,13 +27,6 @@ def api():
 def _torch():
     import torch
     return torch
-
-
-def bf16_round(a):
-    a = np.asarray(a, np.float32)
-    u = a.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 @pytest.mark.parametrize("prob", [synth.uniform_problem(3, [5, 6, 4], 3, geometry=synth.warped_geometry(3),
@@ -59,7 +52,91 @@ def _random_batch(n, seed):
     return feat, target
 
 
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def network(theta, f, target, rf=None, rW1=None, rh1=None, rW2=None, rdz2=None, rdz1=None):
+    """The network and its gradient with optional maps applied to the operands
+    of the five matrix products (forward: f W1^T, h1 W2^T; back-propagation:
+    dz2^T h1, dz2 W2, dz1^T f).  One map per operand, shared by every product
+    that reads it (the device rounds each operand once).  Test-side
+    error model of the BF16 products; without maps it is the exact network."""
+    idn = lambda a: a
+    rf, rW1, rh1, rW2, rdz2, rdz1 = [m or idn for m in (rf, rW1, rh1, rW2, rdz2, rdz1)]
+    P = omlp.unpack(theta)
+    fr, W2r = rf(f), rW2(P["W2"])
+    h1 = np.tanh(fr @ rW1(P["W1"]).T + P["b1"])
+    h1r = rh1(h1)
+    h2 = np.tanh(h1r @ W2r.T + P["b2"])
+    t = h2 @ P["w3"] + P["b3"][0]
+    n = len(t)
+    dt = 2.0 * (t - target) / n
+    g = {"w3": h2.T @ dt, "b3": np.array([dt.sum()])}
+    dz2 = np.outer(dt, P["w3"]) * (1.0 - h2 * h2)
+    dz2r = rdz2(dz2)
+    g["W2"] = dz2r.T @ h1r
+    g["b2"] = dz2.sum(axis=0)
+    dz1 = (dz2r @ W2r) * (1.0 - h1 * h1)
+    g["W1"] = rdz1(dz1).T @ fr
+    g["b1"] = dz1.sum(axis=0)
+    return t, omlp.pack(g)
+
+
+def rounding_scale(theta, f, target, samples=64, seed=0):
+    """Statistical scale of the BF16 rounding error of every output (Higham and
+    Mary's probabilistic model of rounding: each rounded operand is x (1 + d)
+    with independent d, |d| <= u = 2^-8).  The first-order error of an output
+    is then a sum of many independent terms, and its spread is estimated by
+    evaluating the network with d drawn uniformly from [-u, u] for every
+    rounded operand, `samples` times: returns the per-entry standard deviation
+    of t and of the packed gradient around the exact values."""
+    rng = np.random.default_rng(seed)
+    ts, gs = [], []
+    for _ in range(samples):
+        maps = [lambda a: a * (1.0 + rng.uniform(-U_BF16, U_BF16, np.shape(a))) for _ in range(6)]
+        t, g = network(theta, f, target, *maps)
+        ts.append(t)
+        gs.append(g)
+    t0, g0 = network(theta, f, target)
+    st = np.sqrt(np.mean((np.array(ts) - t0) ** 2, axis=0))
+    sg = np.sqrt(np.mean((np.array(gs) - g0) ** 2, axis=0))
+    return st, sg
+
+
+def fp32_allowance(theta, f, target):
+    """Deterministic bound of FP32 accumulation: a sum of K terms evaluated in
+    FP32 is off by at most K 2^-24 times the sum of the terms' magnitudes
+    (first order).  Returns the allowances for t and the packed gradient."""
+    P = omlp.unpack(theta)
+    t, (f, h1, h2) = omlp.forward(theta, np.zeros(8), np.ones(8), f)
+    n = len(t)
+    adt = np.abs(2.0 * (t - target) / n)
+    adz2 = np.outer(adt, np.abs(P["w3"])) * np.abs(1.0 - h2 * h2)
+    adz1 = (adz2 @ np.abs(P["W2"])) * np.abs(1.0 - h1 * h1)
+    g = {"w3": np.abs(h2).T @ adt, "b3": np.array([adt.sum()]), "W2": adz2.T @ np.abs(h1), "b2": adz2.sum(0),
+         "W1": adz1.T @ np.abs(f), "b1": adz1.sum(0)}
+    a_t = 64 * U_FP32 * (np.abs(h2) @ np.abs(P["w3"]) + np.abs(P["b3"][0])) + 4 * U_FP32 * np.abs(t)
+    return a_t, n * U_FP32 * omlp.pack(g)
+
+
 def test_forward_and_gradient_match_fp64(api):
+    """Two checks of the BF16 network: (1) against the same network with its
+    product operands rounded to BF16 at the places the device rounds them (a
+    test-side model; only FP32 accumulation order and tanhf differ): 1e-3
+    relative per parameter block; (2) against the exact FP64 oracle, entry by
+    entry, within 12 standard deviations of the statistical rounding error
+    plus the FP32 accumulation bound.  Why 12: BF16 rounding of values near
+    +-1 after tanh goes the same way for many samples, a correlation the
+    independent model leaves out; with exact round-to-nearest-even operands
+    on the host (six seeds, Glorot weights) the weight gradients stay within
+    2.7 sigma and the bias gradients, sums over all samples, within 8.5 sigma,
+    while flipping the sign of one gradient entry moves it by 26 to 1200
+    sigma."""
     torch = _torch()
     m = api.igafd_mlp_create(seed=5)
     n = 1000  # several 16-sample groups per wave and a ragged tail
@@ -72,25 +149,31 @@ def test_forward_and_gradient_match_fp64(api):
     theta = params[:npar].astype(np.float64)
     mean, inv_std = params[npar:npar + 8].astype(np.float64), params[npar + 8:].astype(np.float64)
     np.testing.assert_allclose(mean, feat.mean(0), rtol=1e-5, atol=1e-6)
-    # the device normalises in FP32 and feeds BF16-rounded operands to every
-    # matrix product; the oracle gets the same normalised inputs and rounding
+    # the device normalises in FP32 with its own mean and 1/std; the models
+    # take the same normalised inputs
     fn = ((feat - params[npar:npar + 8]) * params[npar + 8:]).astype(np.float32).astype(np.float64)
+    tgt = target.astype(np.float64)
     zero, one = np.zeros(8), np.ones(8)
-    t_ref, _ = omlp.forward(theta, zero, one, fn, rnd=bf16_round)
+    t_ex, _ = omlp.forward(theta, zero, one, fn)
+    L_ex, g_ex = omlp.loss_and_grad(theta, zero, one, fn, tgt)
+    t_rn, g_rn = network(theta, fn, tgt, *([bf16_round] * 6))
+    s_t, s_g = rounding_scale(theta, fn, tgt)
+    a_t, a_g = fp32_allowance(theta, fn, tgt)
     tout = torch.empty(n, dtype=torch.float32, device="cuda")
     api.igafd_mlp_forward(m, fd_, n, t=tout)
-    # FP32 accumulation order, tanhf vs tanh: an occasional one-ulp BF16 flip
-    assert np.max(np.abs(to_host(tout) - t_ref)) <= 1e-3 * max(1.0, np.abs(t_ref).max())
-    L_ref, g_ref = omlp.loss_and_grad(theta, zero, one, fn, target, rnd=bf16_round)
-    _, g_exact = omlp.loss_and_grad(theta, zero, one, fn, target)
+    tg = to_host(tout).astype(np.float64)
+    assert np.max(np.abs(tg - t_rn)) <= 1e-3 * max(1.0, np.abs(t_rn).max())
+    assert np.all(np.abs(tg - t_ex) <= 12 * s_t + a_t), np.max(np.abs(tg - t_ex) / s_t)
     L, g = api.igafd_mlp_gradient(m, fd_, td, n)
-    assert abs(L - L_ref) <= 1e-3 * L_ref
+    g = g.astype(np.float64)
+    assert abs(L - L_ex) <= 1e-2 * L_ex
     k = 0
     for name, shape in omlp.SIZES:
         size = int(np.prod(shape))
-        a = g[k:k + size].astype(np.float64)
-        assert rel(a, g_ref[k:k + size]) < 1e-3, (name, rel(a, g_ref[k:k + size]))
-        assert rel(a, g_exact[k:k + size]) < 1e-1, (name, rel(a, g_exact[k:k + size]))
+        sl = slice(k, k + size)
+        assert rel(g[sl], g_rn[sl]) < 1e-3, (name, rel(g[sl], g_rn[sl]))
+        err = np.abs(g[sl] - g_ex[sl])
+        assert np.all(err <= 12 * s_g[sl] + a_g[sl]), (name, np.max(err / s_g[sl]))
         k += size
     m.close()
 
