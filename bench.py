@@ -406,20 +406,32 @@ def run_learned(args, api, torch, synth):
     log(f"trained on {total} dofs of {args.train} problems in {t_train:.1f}s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     E, p = args.elements or 112, args.degree or 4
     prob = synth.learned_eval_problem(E=E, p=p)
-    ctx = api.igafd_setup(prob)
+    # the setup's cost of the features: the same setup without and with them
+    t0 = time.perf_counter()
+    api.igafd_setup(prob).close()
+    torch.cuda.synchronize()
+    t_setup_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx = api.igafd_setup(prob, features=True)
+    torch.cuda.synchronize()
+    t_setup_feat = time.perf_counter() - t0
     b = rhs(api, torch, synth, ctx)
     u = torch.zeros_like(b)
     res = {}
     ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1)
     res["plain"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"]}
+    scaling.predict_scaling(mlp, ctx)  # warm-up (first launches of the network kernels)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     scaling.predict_scaling(mlp, ctx)
     torch.cuda.synchronize()
     t_pred = time.perf_counter() - t1
+    feat_setup = max(0.0, t_setup_feat - t_setup_plain)
     times, infos = timed_solves(api, torch, ctx, b, u, args.steps, args.warmup, use_scaling=True)
     res["learned"] = {"s": float(np.median(times)), "iters": infos[-1]["iters"],
                       "true_relres": infos[-1]["true_relres"], "fallback": infos[-1]["fallback"],
-                      "predict_s": t_pred}
+                      "predict_s": t_pred, "features_setup_s": feat_setup,
+                      "setup_s": {"without_features": t_setup_plain, "with_features": t_setup_feat}}
     api.igafd_set_scaling_diag_ratio(ctx)
     ts, inf = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1, use_scaling=True)
     res["exact_ratio"] = {"s": float(np.median(ts)), "iters": inf[-1]["iters"], "true_relres": inf[-1]["true_relres"]}

@@ -95,6 +95,9 @@ typedef struct {
   int n_coef_params;
   const double* coef_params;   /* host, see IGAFD_COEF_*                                       */
   int quad_per_dir;            /* Gauss points per element and direction: 0 or p+1             */
+  int want_features;           /* 1: igafd_setup also sums the per-dof inputs of the learned
+                                  scaling (igafd_features) from the Gauss-point values it
+                                  evaluates for A, and keeps them (8N floats)                  */
 } igafd_problem;
 
 /*
@@ -341,7 +344,10 @@ igafd_status igafd_lshape_corner(const igafd_ctx* ctx, int* hole, long long* ndo
 
 /* Per-dof inputs, N x 8 FP32 (device): the B_i-weighted quadrature averages
  * over supp B_i of the entries (11, 22, 33, 12, 13, 23) of |det J| J^-1 J^-T
- * and of kappa, then the degree p. */
+ * and of kappa, then the degree p.  A context set up with want_features
+ * copies the ones it assembled with A; otherwise they are computed now
+ * (allocates and frees an accumulator of 8N doubles, synchronises the
+ * stream). */
 igafd_status igafd_features(igafd_ctx* ctx, float* feat_dev);
 
 /* Training targets t_i = 1/2 log(P_ii / A_ii) (N floats, device). */

@@ -37,7 +37,7 @@ class igafd_problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("nknots", C.c_int * 3),
                 ("knots", C.POINTER(C.c_double) * 3), ("geom_kind", C.c_int), ("n_geom_params", C.c_int),
                 ("geom_params", C.POINTER(C.c_double)), ("coef_kind", C.c_int), ("n_coef_params", C.c_int),
-                ("coef_params", C.POINTER(C.c_double)), ("quad_per_dir", C.c_int)]
+                ("coef_params", C.POINTER(C.c_double)), ("quad_per_dir", C.c_int), ("want_features", C.c_int)]
 
 
 class igafd_solve_opts(C.Structure):
@@ -216,9 +216,10 @@ class Context:
         self.close()
 
 
-def igafd_setup(problem: dict, stream=None) -> Context:
-    """Setup of one problem (host 1D setup + device assembly)."""
-    return _setup(problem, stream, "igafd_setup")
+def igafd_setup(problem: dict, stream=None, features=False) -> Context:
+    """Setup of one problem (host 1D setup + device assembly); features=True
+    also assembles the learned scaling's per-dof inputs."""
+    return _setup(problem, stream, "igafd_setup", features)
 
 
 def igafd_setup_precond(problem: dict, stream=None) -> Context:
@@ -227,7 +228,7 @@ def igafd_setup_precond(problem: dict, stream=None) -> Context:
     return _setup(problem, stream, "igafd_setup_precond")
 
 
-def _setup(problem: dict, stream, entry: str) -> Context:
+def _setup(problem: dict, stream, entry: str, features=False) -> Context:
     d = int(problem["dim"])
     pr = igafd_problem()
     pr.dim = d
@@ -248,6 +249,7 @@ def _setup(problem: dict, stream, entry: str) -> Context:
     pr.geom_kind, pr.n_geom_params, pr.geom_params = gk, len(gp), gpa
     pr.coef_kind, pr.n_coef_params, pr.coef_params = ck, len(cp), cpa
     pr.quad_per_dir = int(problem.get("quad", 0) or 0)
+    pr.want_features = int(bool(features))
     h = C.c_void_p()
     _check(getattr(lib(), entry)(C.byref(pr), stream if stream is not None else _current_stream(), C.byref(h)))
     n, N, nnz, bb = igafd_sizes(h)

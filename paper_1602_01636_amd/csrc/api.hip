@@ -30,6 +30,14 @@ thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 
+// Block partials every reduction of a context may write (per sum): the
+// vector kernels' grid, every FD path and tile count, and at least 1025 (the
+// spectral bounds' blocks plus their result).
+int partial_capacity(const igafd_ctx* c) {
+  const int vb = (int)((c->N + kBlock - 1) / kBlock);
+  return std::max(std::max(vb, 1025), fd_dot_blocks_max(c));
+}
+
 namespace {
 
 enum { RED_BB_RR = 0, RED_PQ = 1, RED_RR = 2, RED_RZ = 3, RED_RHO0 = 4, RED_TRUE = 5 };
@@ -169,6 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
 void free_dev(void* p) {
   if (p) (void)hipFree(p);
 }
+
+unsigned vblocks(const igafd_ctx* c) { return (unsigned)((c->N + kBlock - 1) / kBlock); }
 
 template <typename T>
 igafd_status dev_upload(T** dst, const T* src, size_t count, hipStream_t st) {
@@ -355,8 +365,6 @@ igafd_status parse_geometry(const igafd_problem* pr, GeomDesc* g) {
   return IGAFD_OK;
 }
 
-unsigned vblocks(const igafd_ctx* c) { return (unsigned)((c->N + kBlock - 1) / kBlock); }
-
 igafd_status alloc_workspace(igafd_ctx* c) {
   const size_t vb = sizeof(double) * (size_t)c->N;
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->r, vb));
@@ -373,7 +381,7 @@ igafd_status alloc_workspace(igafd_ctx* c) {
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[1], vb));
   // partial sums: one (or two) per block of every reduction kernel, for any
   // kernel shape the autotuner may pick
-  c->npartial = std::max((int)vblocks(c), fd_dot_blocks_max(c));
+  c->npartial = partial_capacity(c);
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
   IGAFD_HIP_CHECK(hipMalloc((void**)&c->state, sizeof(SolverState)));
   IGAFD_HIP_CHECK(hipHostMalloc((void**)&c->hstate, sizeof(SolverState), hipHostMallocDefault));
@@ -1002,6 +1010,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
   c->dim = pr->dim;
   c->p = pr->degree;
   c->stream = (hipStream_t)stream;
+  IGAFD_HIP_CHECK(hipGetDevice(&c->device));
   const int q = pr->quad_per_dir > 0 ? pr->quad_per_dir : pr->degree + 1;
   igafd_status s;
   if ((s = parse_geometry(pr, &c->geom)) != IGAFD_OK) return s;
@@ -1030,7 +1039,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
     // FD intermediates (FP64 is the widest) and the block partials of the
     // preconditioner's (r, s) product and of the spectral bounds
     for (int b = 0; b < 2; ++b) IGAFD_HIP_CHECK(hipMalloc((void**)&c->fdbuf[b], sizeof(double) * (size_t)c->N));
-    c->npartial = std::max(1025, fd_dot_blocks_max(c.get()));
+    c->npartial = partial_capacity(c.get());
     IGAFD_HIP_CHECK(hipMalloc((void**)&c->partial, sizeof(double) * 2 * (size_t)c->npartial));
     IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
     c->t_setup_ms = elapsed_ms(t_start);
@@ -1052,7 +1061,7 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
     }
     if ((s = spmv_set_tile(c.get(), b2, b3)) != IGAFD_OK) return s;
   }
-  if ((s = assemble_band(c.get())) != IGAFD_OK) return s;
+  if ((s = assemble_band(c.get(), pr->want_features != 0)) != IGAFD_OK) return s;
   IGAFD_HIP_CHECK(hipStreamSynchronize(c->stream));
   c->t_setup_ms = elapsed_ms(t_start);
   *out = c.release();
@@ -1103,6 +1112,7 @@ void igafd_destroy(igafd_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   free_dev(c->hist);
+  free_dev(c->feat);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   delete c;
 }

@@ -107,10 +107,59 @@ __host__ __device__ constexpr int sym_index(int a, int b) {
   return (a == b) ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
 }
 
-template <int D, int P>
+// Per-dof statistics of the learned scaling, one element's share: for the
+// four channels ch0..ch0+3 and every local function a = (a1, a2, a3) of the
+// element, sum_t B_a(t) v(ch, t) over the element's Gauss points t, where
+// v(ch, t) = w_t G_ch(t) (ch < 6: the entries 11, 22, 33, 12, 13, 23 of
+// G = |det J| J^-1 J^-T), w_t kappa(t) (ch = 6) or w_t (ch = 7).  The sum is
+// taken one direction at a time (sum factorisation: t1, then t2, then t3)
+// and added into acc[8 row + ch] for the functions that are dofs; the
+// element's colour class guarantees no other block adds to those rows.  F1
+// (4 L Q Q3 doubles) and F2 (4 L L Q3) are LDS scratch.
+template <int D, int P, typename V>
+__device__ void feature_sums4(int ch0, V v, const double (*sV)[P + 1][P + 1], const int* first, const Tables& T,
+                              double* F1, double* F2, double* __restrict__ acc) {
+  constexpr int Q = P + 1, L = P + 1;
+  constexpr int Q3 = (D == 3) ? Q : 1;
+  constexpr int L3 = (D == 3) ? L : 1;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 4 * L * Q * Q3; idx += kBlock) {  // F1[c][t2 + Q t3][a1]
+    const int c = idx / (L * Q * Q3), r = idx % (L * Q * Q3);
+    const int a1 = r % L, t23 = r / L;
+    double s = 0.0;
+#pragma unroll
+    for (int t1 = 0; t1 < Q; ++t1) s += sV[0][t1][a1] * v(ch0 + c, t1 + Q * t23);
+    F1[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 4 * L * L * Q3; idx += kBlock) {  // F2[c][t3][a2][a1]
+    const int c = idx / (L * L * Q3), r = idx % (L * L * Q3);
+    const int a1 = r % L, a2 = (r / L) % L, t3 = r / (L * L);
+    double s = 0.0;
+#pragma unroll
+    for (int t2 = 0; t2 < Q; ++t2) s += sV[1][t2][a2] * F1[c * (L * Q * Q3) + (t2 + Q * t3) * L + a1];
+    F2[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 4 * L * L * L3; idx += kBlock) {
+    const int c = idx / (L * L * L3), r = idx % (L * L * L3);
+    const int a1 = r % L, a2 = (r / L) % L, a3 = r / (L * L);
+    const int r1 = first[0] + a1 - 1, r2 = first[1] + a2 - 1, r3 = (D == 3) ? first[2] + a3 - 1 : 0;
+    if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int t3 = 0; t3 < Q3; ++t3) s += sV[2][t3][a3] * F2[c * (L * L * Q3) + (t3 * L + a2) * L + a1];
+    acc[8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)) + ch0 + c] += s;
+  }
+  __syncthreads();
+}
+
+// FEAT = 1: also the per-dof feature sums of the learned scaling into acc
+// (8 doubles per dof), from the same Gauss-point evaluation of the map.
+template <int D, int P, int FEAT>
 __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, double* __restrict__ band,
                                                      long long Ns, int c1, int c2, int c3, int m1, int m2,
-                                                     int* __restrict__ err) {
+                                                     int* __restrict__ err, double* __restrict__ acc) {
   constexpr int Q = P + 1, L = P + 1;
   constexpr int Q3 = (D == 3) ? Q : 1;
   constexpr int L3 = (D == 3) ? L : 1;
@@ -128,6 +177,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
   __shared__ double sH[NAB][Q * Q];
   __shared__ double sG[NAB][L * L][Q];
   __shared__ int sFirst[3];
+  // features: kappa and the weight per point, F2 of the contraction (F1 lives in sG)
+  __shared__ double sKap[FEAT ? NQ : 1], sW[FEAT ? NQ : 1];
+  __shared__ double sF2[FEAT ? 4 * L * L * Q3 : 1];
+  static_assert(!FEAT || NAB * L * L * Q >= 4 * L * Q * Q3, "feature scratch F1 must fit in sG");
 
   int bid = blockIdx.x;
   const int j1 = bid % m1;
@@ -161,15 +214,32 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
     map_eval<D>(g, xi, x, J);
     const double det = adjugate<D>(J, A);
     if (!(det > 0.0)) *err = 1;
-    const double f = w * kappa_eval(g, x) / fabs(det);
+    const double kap = kappa_eval(g, x);
+    const double f = w * kap / fabs(det);
     for (int a = 0; a < D; ++a)
       for (int b = a; b < D; ++b) {
         double s = 0.0;
         for (int k = 0; k < D; ++k) s += A[a][k] * A[b][k];
         sC[sym_index<D>(a, b)][t] = f * s;
       }
+    if (FEAT) {
+      sKap[t] = kap;
+      sW[t] = w;
+    }
   }
   __syncthreads();
+  if (FEAT) {
+    // w G_ab = C_ab / kappa; the channel order is (11, 22, 33, 12, 13, 23, kappa, 1)
+    auto v = [&](int ch, int t) -> double {
+      if (ch == 6) return sW[t] * sKap[t];
+      if (ch == 7) return sW[t];
+      constexpr int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+      if (ia[ch] >= D || ib[ch] >= D) return 0.0;
+      return sC[sym_index<D>(ia[ch], ib[ch])][t] / sKap[t];
+    };
+    feature_sums4<D, P>(0, v, sV, sFirst, T, &sG[0][0][0], sF2, acc);
+    feature_sums4<D, P>(4, v, sV, sFirst, T, &sG[0][0][0], sF2, acc);
+  }
 
   for (int a3 = 0; a3 < L3; ++a3) {
     for (int b3 = a3; b3 < L3; ++b3) {
@@ -310,19 +380,19 @@ __global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, RhsDesc r
   }
 }
 
-// Per-dof geometry/coefficient statistics for the learned scaling: the
-// B_i-weighted quadrature averages over supp B_i of the six entries of
-// G = |det J| J^-1 J^-T (= Q / kappa, Sec. 2.1 eq. Q) and of kappa.  One colour
-// class of elements adds w_t B_i(t) (G_c(t), kappa(t), 1) into acc[i][0..7].
+// Per-dof geometry/coefficient statistics for the learned scaling, without
+// assembling A: the same Gauss-point values as k_assemble's feature channels
+// (w G's six entries, w kappa, w), summed into acc by feature_sums4.
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, double* __restrict__ acc, int c1, int c2,
                                                      int c3, int m1, int m2) {
   constexpr int Q = P + 1, L = P + 1;
   constexpr int Q3 = (D == 3) ? Q : 1;
-  constexpr int L3 = (D == 3) ? L : 1;
   constexpr int NQ = Q * Q * Q3;
   __shared__ double sf[8][NQ];
   __shared__ double sV[3][Q][L];
+  __shared__ double sF1[4 * L * Q * Q3], sF2[4 * L * L * Q3];
+  __shared__ int sFirst[3];
   int bid = blockIdx.x;
   const int j1 = bid % m1;
   bid /= m1;
@@ -334,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, doubl
     const int l = idx / (Q * L), t = (idx / L) % Q, a = idx % L;
     sV[l][t][a] = (l < D) ? T.val[l][(e[l] * Q + t) * L + a] : ((t == 0 && a == 0) ? 1.0 : 0.0);
   }
+  if (tid < 3) sFirst[tid] = (tid < D) ? T.first[tid][e[tid]] : 1;
   for (int t = tid; t < NQ; t += kBlock) {
     const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
     double xi[3] = {T.qx[0][e[0] * Q + t1], T.qx[1][e[1] * Q + t2], 0.0};
@@ -362,22 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, doubl
     sf[7][t] = w;
   }
   __syncthreads();
-  for (int idx = tid; idx < L * L * L3; idx += kBlock) {
-    const int a1 = idx % L, a2 = (idx / L) % L, a3 = idx / (L * L);
-    const int r1 = T.first[0][e[0]] + a1 - 1, r2 = T.first[1][e[1]] + a2 - 1;
-    const int r3 = (D == 3) ? T.first[2][e[2]] + a3 - 1 : 0;
-    if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = 0; t < NQ; ++t) {
-      const int t1 = t % Q, t2 = (t / Q) % Q, t3 = t / (Q * Q);
-      const double bv = sV[0][t1][a1] * sV[1][t2][a2] * sV[2][t3][a3];
-#pragma unroll
-      for (int ch = 0; ch < 8; ++ch) s[ch] += sf[ch][t] * bv;
-    }
-    double* o = acc + 8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3));
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch) o[ch] += s[ch];
-  }
+  auto v = [&](int ch, int t) -> double { return sf[ch][t]; };
+  feature_sums4<D, P>(0, v, sV, sFirst, T, sF1, sF2, acc);
+  feature_sums4<D, P>(4, v, sV, sFirst, T, sF1, sF2, acc);
 }
 
 // Extreme eigenvalues of a symmetric positive definite 2x2 / 3x3 matrix.
@@ -502,33 +560,27 @@ __global__ void k_features_finish(const double* __restrict__ acc, float* __restr
   feat[8 * i + 7] = (float)p;
 }
 
-// S_i = sqrt(P_ii / A_ii): the diagonal-ratio scaling
-__global__ void k_sqrt_ratio(const double* __restrict__ band0, const double* __restrict__ dP, double* __restrict__ S,
-                             long long N) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) S[i] = sqrt(dP[i] / band0[i]);
+// diag(P)_i = sum_j K_j[i_j, i_j] prod_{l != j} M_l[i_l, i_l]  (Sec. 3 Kronecker sum)
+__device__ inline double diagP_at(const double* m1, const double* k1, const double* m2, const double* k2,
+                                  const double* m3, const double* k3, int n1, int n2, int dim, long long i) {
+  const int i1 = (int)(i % n1);
+  const long long t = i / n1;
+  const int i2 = (int)(t % n2), i3 = (int)(t / n2);
+  if (dim == 2) return k1[i1] * m2[i2] + m1[i1] * k2[i2];
+  return k1[i1] * m2[i2] * m3[i3] + m1[i1] * k2[i2] * m3[i3] + m1[i1] * m2[i2] * k3[i3];
 }
 
-// t_i = 1/2 log(P_ii / A_ii): the log of the diagonal-ratio scaling
-__global__ void k_log_ratio(const double* __restrict__ band0, const double* __restrict__ dP, float* __restrict__ t,
-                            long long N) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) t[i] = (float)(0.5 * log(dP[i] / band0[i]));
-}
-
-// diag(P) = sum_j K_j[i_j, i_j] prod_{l != j} M_l[i_l, i_l]  (Sec. 3 Kronecker sum)
 __global__ void k_diagP(const double* m1, const double* k1, const double* m2, const double* k2,
                         const double* m3, const double* k3, int n1, int n2, long long N, int dim,
                         double* out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int i1 = (int)(i % n1);
-  const long long t = i / n1;
-  const int i2 = (int)(t % n2), i3 = (int)(t / n2);
-  if (dim == 2)
-    out[i] = k1[i1] * m2[i2] + m1[i1] * k2[i2];
-  else
-    out[i] = k1[i1] * m2[i2] * m3[i3] + m1[i1] * k2[i2] * m3[i3] + m1[i1] * m2[i2] * k3[i3];
+  if (i < N) out[i] = diagP_at(m1, k1, m2, k2, m3, k3, n1, n2, dim, i);
+}
+
+// a fill kernel instead of a memset: callers may capture these launches into graphs
+__global__ void k_zero(double* __restrict__ p, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0;
 }
 
 __global__ void k_copy_plane(const double* __restrict__ src, double* __restrict__ dst, long long N) {
@@ -550,7 +602,7 @@ Tables make_tables(const igafd_ctx* c) {
 }
 
 template <int D, int P>
-igafd_status launch_assemble(igafd_ctx* c) {
+igafd_status launch_assemble(igafd_ctx* c, double* acc) {
   const Tables T = make_tables(c);
   const int nel[3] = {c->ddir[0].nel, c->ddir[1].nel, D == 3 ? c->ddir[2].nel : 1};
   const int C3 = (D == 3) ? P + 1 : 1;
@@ -562,8 +614,12 @@ igafd_status launch_assemble(igafd_ctx* c) {
         const int m3 = (D == 3) ? (c3 < nel[2] ? (nel[2] - c3 + P) / (P + 1) : 0) : 1;
         const long long blocks = (long long)m1 * m2 * m3;
         if (blocks == 0) continue;
-        hipLaunchKernelGGL((k_assemble<D, P>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom,
-                           c->band + c->halo, c->Ns, c1, c2, c3, m1, m2, c->dflag);
+        if (acc)
+          hipLaunchKernelGGL((k_assemble<D, P, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom,
+                             c->band + c->halo, c->Ns, c1, c2, c3, m1, m2, c->dflag, acc);
+        else
+          hipLaunchKernelGGL((k_assemble<D, P, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, c->stream, T, c->geom,
+                             c->band + c->halo, c->Ns, c1, c2, c3, m1, m2, c->dflag, nullptr);
         IGAFD_HIP_CHECK(hipGetLastError());
       }
   return IGAFD_OK;
@@ -626,7 +682,7 @@ igafd_status dispatch(int dim, int p, Args... args) {
 
 template <int D, int P>
 struct AssembleOp {
-  static igafd_status run(igafd_ctx* c) { return launch_assemble<D, P>(c); }
+  static igafd_status run(igafd_ctx* c, double* acc) { return launch_assemble<D, P>(c, acc); }
 };
 template <int D, int P>
 struct FeatureOp {
@@ -639,10 +695,28 @@ struct LoadOp {
 
 }  // namespace
 
-igafd_status assemble_band(igafd_ctx* c) {
+igafd_status assemble_band(igafd_ctx* c, bool with_features) {
   IGAFD_HIP_CHECK(hipMemsetAsync(c->band, 0, sizeof(double) * c->H * c->Ns, c->stream));
   IGAFD_HIP_CHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
-  igafd_status st = dispatch<AssembleOp>(c->dim, c->p, c);
+  double* acc = nullptr;
+  if (with_features) {  // feature sums (8 per dof) assembled with A, kept as FP32 features
+    IGAFD_HIP_CHECK(hipMalloc((void**)&acc, sizeof(double) * 8 * (size_t)c->N));
+    IGAFD_HIP_CHECK(hipMalloc((void**)&c->feat, sizeof(float) * 8 * (size_t)c->N));
+    IGAFD_HIP_CHECK(hipMemsetAsync(acc, 0, sizeof(double) * 8 * (size_t)c->N, c->stream));
+  }
+  igafd_status st = dispatch<AssembleOp>(c->dim, c->p, c, acc);
+  if (st == IGAFD_OK && acc) {
+    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_features_finish, dim3(blocks), dim3(kBlock), 0, c->stream, acc, c->feat, c->N, c->p);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("feature finish kernel failed");
+      st = IGAFD_ERR_HIP;
+    }
+  }
+  if (acc) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(acc);
+  }
   if (st != IGAFD_OK) return st;
   int flag = 0;
   IGAFD_HIP_CHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -727,48 +801,63 @@ igafd_status diagonals(igafd_ctx* c, double* dA, double* dP) {
 }
 
 igafd_status features(igafd_ctx* c, float* feat) {
+  if (c->feat) {  // assembled with A at setup
+    IGAFD_HIP_CHECK(
+        hipMemcpyAsync(feat, c->feat, sizeof(float) * 8 * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    return IGAFD_OK;
+  }
   double* acc = nullptr;
   IGAFD_HIP_CHECK(hipMalloc((void**)&acc, sizeof(double) * 8 * (size_t)c->N));
-  igafd_status st = IGAFD_OK;
-  if (hipMemsetAsync(acc, 0, sizeof(double) * 8 * (size_t)c->N, c->stream) != hipSuccess) st = IGAFD_ERR_HIP;
-  if (st == IGAFD_OK) st = dispatch<FeatureOp>(c->dim, c->p, c, acc);
-  if (st == IGAFD_OK) {
-    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_features_finish, dim3(blocks), dim3(kBlock), 0, c->stream, acc, feat, c->N, c->p);
-    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
-  }
+  igafd_status st = features_into(c, acc, feat);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(acc);
-  if (st == IGAFD_ERR_HIP) set_error("feature kernels failed");
   return st;
+}
+
+igafd_status features_into(igafd_ctx* c, double* acc, float* feat) {
+  const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((8 * c->N + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, acc,
+                     8 * c->N);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  igafd_status st = dispatch<FeatureOp>(c->dim, c->p, c, acc);
+  if (st != IGAFD_OK) return st;
+  hipLaunchKernelGGL(k_features_finish, dim3(blocks), dim3(kBlock), 0, c->stream, acc, feat, c->N, c->p);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+// t_i = 1/2 log(P_ii / A_ii) (log = 1) or S_i = sqrt(P_ii / A_ii) (log = 0),
+// diag(P) from the univariate diagonals (Sec. 3 Kronecker sum)
+__global__ void k_diag_ratio(const double* __restrict__ band0, const double* m1, const double* k1, const double* m2,
+                             const double* k2, const double* m3, const double* k3, int n1, int n2, long long N,
+                             int dim, int log_form, float* __restrict__ t, double* __restrict__ S) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double dP = diagP_at(m1, k1, m2, k2, m3, k3, n1, n2, dim, i);
+  if (log_form)
+    t[i] = (float)(0.5 * log(dP / band0[i]));
+  else
+    S[i] = sqrt(dP / band0[i]);
 }
 
 igafd_status scaling_targets(igafd_ctx* c, float* t) {
-  double* dP = nullptr;
-  IGAFD_HIP_CHECK(hipMalloc((void**)&dP, sizeof(double) * (size_t)c->N));
-  igafd_status st = diagonals(c, nullptr, dP);
-  if (st == IGAFD_OK) {
-    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_log_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, dP, t, c->N);
-    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
-  }
-  (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(dP);
-  return st;
+  const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+  const DevDir* d = c->ddir;
+  hipLaunchKernelGGL(k_diag_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, d[0].diagM,
+                     d[0].diagK, d[1].diagM, d[1].diagK, d[2].diagM, d[2].diagK, c->n[0], c->n[1], c->N, c->dim, 1, t,
+                     nullptr);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
 }
 
 igafd_status diag_ratio_scaling(igafd_ctx* c, double* S) {
-  double* dP = nullptr;
-  IGAFD_HIP_CHECK(hipMalloc((void**)&dP, sizeof(double) * (size_t)c->N));
-  igafd_status st = diagonals(c, nullptr, dP);
-  if (st == IGAFD_OK) {
-    const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_sqrt_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, dP, S, c->N);
-    if (hipGetLastError() != hipSuccess) st = IGAFD_ERR_HIP;
-  }
-  (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(dP);
-  return st;
+  const unsigned blocks = (unsigned)((c->N + kBlock - 1) / kBlock);
+  const DevDir* d = c->ddir;
+  hipLaunchKernelGGL(k_diag_ratio, dim3(blocks), dim3(kBlock), 0, c->stream, c->band + c->halo, d[0].diagM,
+                     d[0].diagK, d[1].diagM, d[1].diagK, d[2].diagM, d[2].diagK, c->n[0], c->n[1], c->N, c->dim, 0,
+                     nullptr, S);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
 }
 
 }  // namespace igafd

@@ -9,6 +9,8 @@
 
 #include "igafd.h"
 
+struct igafd_ctx;
+
 namespace igafd {
 
 constexpr int kMaxDegree = 6;
@@ -17,6 +19,8 @@ constexpr int kBlock = 256;
 constexpr long long kTileLdsDefault = 80 * 1024;  // two tiled-product blocks per CU (160 KB LDS)
 
 void set_error(const std::string& msg);
+// block partials (per sum) a context's reductions may write; sizes its buffer
+int partial_capacity(const igafd_ctx* c);
 
 #define IGAFD_HIP_CHECK(expr)                                                        \
   do {                                                                              \
@@ -100,6 +104,7 @@ struct igafd_ctx {
   int n[3] = {1, 1, 1};
   long long N = 0;
   hipStream_t stream = nullptr;
+  int device = 0;                          // device current at setup
   igafd::GeomDesc geom{};
   igafd::Dir1D dir[3];
   igafd::DevDir ddir[3];
@@ -139,6 +144,7 @@ struct igafd_ctx {
   igafd::SolverState* hstate = nullptr;    // pinned host mirror
   int* dflag = nullptr;                    // device error flag (geometry)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float* feat = nullptr;                   // per-dof features (N x 8) assembled with A, when asked for
   double* hist = nullptr;                  // device residual history of igafd_solve
   int hist_alloc = 0;                      // doubles allocated at hist
   double t_setup_ms = 0.0;                 // host wall time of the setup
@@ -156,10 +162,13 @@ struct igafd_ctx {
 
 namespace igafd {
 // assembly.hip
-igafd_status assemble_band(igafd_ctx* c);
+igafd_status assemble_band(igafd_ctx* c, bool with_features);
 igafd_status assemble_load(igafd_ctx* c, int rhs_kind, const double* params, int nparams, double* b);
 igafd_status diagonals(igafd_ctx* c, double* dA, double* dP);
 igafd_status features(igafd_ctx* c, float* feat);
+// on-demand features with a caller-given accumulator of 8N doubles (no
+// allocation, no synchronisation)
+igafd_status features_into(igafd_ctx* c, double* acc, float* feat);
 igafd_status scaling_targets(igafd_ctx* c, float* t);
 igafd_status diag_ratio_scaling(igafd_ctx* c, double* S);
 igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* qloc);

@@ -30,7 +30,7 @@ def build_dataset(problems, shuffle_seed=0, log=None):
     targ = torch.empty(total, dtype=torch.float32, device="cuda")
     off = 0
     for k, (pr, n) in enumerate(zip(problems, sizes)):
-        with B.igafd_setup(pr) as ctx:
+        with B.igafd_setup(pr, features=True) as ctx:  # features summed by the assembly itself
             B.igafd_features(ctx, feat[off * 8:(off + n) * 8])
             B.igafd_scaling_targets(ctx, targ[off:off + n])
         off += n
@@ -65,7 +65,9 @@ def train(mlp, feat, targ, total, epochs=20, batch=8192, lr=3e-3, lr_final=3e-4,
 
 
 def predict_scaling(mlp, ctx):
-    """S = exp(MLP(features)) for the problem of ctx, set on ctx; returns S."""
+    """S = exp(MLP(features)) for the problem of ctx, set on ctx; returns S.
+    With a context set up with features=True the features are a copy of
+    what the assembly summed."""
     import torch
     feat = torch.empty(ctx.N * 8, dtype=torch.float32, device="cuda")
     B.igafd_features(ctx, feat)
@@ -77,10 +79,15 @@ def predict_scaling(mlp, ctx):
 
 def train_default(n_train=2000, seed=0, epochs=20, log=None):
     """The standard training run: seeds 0..n_train-1 of synth.training_problem."""
+    import time
+    t0 = time.perf_counter()
     probs = [synth.training_problem(s) for s in range(n_train)]
     feat, targ, total = build_dataset(probs, shuffle_seed=seed, log=log)
+    t1 = time.perf_counter()
     mlp = B.igafd_mlp_create(seed)
     hist = train(mlp, feat, targ, total, epochs=epochs, log=log)
+    if log:
+        log(f"dataset {t1 - t0:.1f} s ({total} dofs), training {time.perf_counter() - t1:.1f} s")
     return mlp, hist, total
 
 

@@ -42,6 +42,11 @@ def test_features_and_targets_match_oracle(api, prob):
         fo = omlp.features(prob)
         np.testing.assert_allclose(to_host(f).reshape(-1, 8), fo, rtol=2e-6, atol=2e-7)
         np.testing.assert_allclose(to_host(t), omlp.targets(prob), rtol=1e-5, atol=1e-6)
+    # the features summed by the assembly kernel itself (want_features)
+    with api.igafd_setup(prob, features=True) as ctx:
+        f2 = torch.empty(ctx.N * 8, dtype=torch.float32, device="cuda")
+        api.igafd_features(ctx, f2)
+        np.testing.assert_allclose(to_host(f2).reshape(-1, 8), fo, rtol=2e-6, atol=2e-7)
 
 
 def _random_batch(n, seed):
