@@ -27,7 +27,12 @@ Other workloads (--workload), each printing one JSON line of the same form:
   cube     unit cube, P = A: the FD apply as the direct solver (the paper's Table cube) at
            h^-1 = 128, 256, 512 (--elements 1024 for the 10^9-unknown case), p = 3 (--degree)
 
+The default run (ring) also carries, as sub-objects, the warped-cube BF16
+comparison ("warped_bf16") and the learned-scaling comparison
+("learned_scaling": training on 2000 small warped cubes, evaluation at 112^3).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+                       [--no-extras]
 """
 from __future__ import annotations
 
@@ -438,6 +443,9 @@ def run_learned(args, api, torch, synth):
     log(f"plain {res['plain']['iters']} learned {res['learned']['iters']} exact {res['exact_ratio']['iters']}")
     qlo, qhi = api.igafd_spectral_bounds(ctx)
     res["plain"]["kappa_bound"] = qhi / qlo
+    use, kq, kl = api.igafd_scaling_gate(ctx)
+    res["gate"] = {"use_scaling": use, "kappa_q": kq, "kappa_loc": kl, "gain": 2.0,
+                   "rule": "scale when (qmax/qmin)/qloc >= gain (Prop. 1 bound vs pointwise anisotropy)"}
     kr = kernel_report(api, torch, ctx, precisions=("fp64",))
     ms_per_step = 1e3 * sum(times) / len(times)
     workload = {"workload": f"warped unit cube (seed 10000), kappa=1+0.5 sin(2pi x)cos(2pi y), p={p}, {E}^3 elements, "
@@ -787,6 +795,8 @@ def main():
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="ring workload only: skip the warped-cube BF16 and learned-scaling sub-objects")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -805,6 +815,30 @@ def main():
            "square": run_square, "lshape": run_lshape, "adi": run_adi, "cube": run_cube,
            "annulus": run_annulus}[args.workload]
     out = run(args, api, torch, synth)
+    if args.workload == "ring" and not args.no_extras:
+        # the two other comparisons the benchmark spec names, on their own workloads
+        # (fewer timed solves; each sub-object carries its own config)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.elements, sub.degree = max(3, args.steps // 4), 1, 0, 0
+        log("== warped cube, p = 5, 96^3: BF16 / split-BF16 / FP32 / FP64 FD")
+        w = run_warped(sub, api, torch, synth)
+        v = w["variants"]
+        fp64_s = v["fp64"]["s"]
+        out["warped_bf16"] = {
+            "config": w["config"], "bf16_s": w["value"], "bf16_iters": w["iters"],
+            "bf16_rel_err_vs_fp64": w["rel_err_vs_fp64"], "variants": v,
+            "speedup_vs_fp64": {pr: fp64_s / (w["value"] if pr == "bf16" else v[pr]["s"])
+                                for pr in ("bf16", "bf16x3", "fp32")},
+            "fd_roofline_bf16": w["fd_roofline"], "kernel_ms": w["kernel_ms"]}
+        log("== learned scaling: train on the small warped cubes, evaluate at 112^3, p = 4")
+        ln = run_learned(sub, api, torch, synth)
+        lv = ln["variants"]
+        saving = lv["plain"]["s"] - lv["learned"]["s"]
+        cost = lv["learned"]["predict_s"] + lv["learned"]["features_setup_s"]
+        out["learned_scaling"] = {
+            "config": ln["config"], "variants": lv, "train_s": ln["train_s"], "train_dofs": ln["train_dofs"],
+            "loss_first_last": ln["loss_first_last"], "saving_per_solve_s": saving,
+            "prediction_cost_s": cost, "pays_off_first_solve": bool(cost < saving)}
     print(json.dumps(out), flush=True)
 
 
