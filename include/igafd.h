@@ -350,6 +350,20 @@ igafd_status igafd_lshape_corner(const igafd_ctx* ctx, int* hole, long long* ndo
  * stream). */
 igafd_status igafd_features(igafd_ctx* ctx, float* feat_dev);
 
+/* igafd_features for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same output as igafd_features; allocates nothing, frees nothing and does
+ * not synchronise (kernel launches on the context's stream only, the
+ * accumulator cleared by a kernel, not a memset).  A context set up with
+ * want_features is copied as by igafd_features; otherwise the feature sums
+ * go through a static device accumulator of 8 doubles per dof for at most
+ * 2^20 = 1,048,576 dofs (64 MiB, held by each GPU the library runs on until
+ * the process ends): a larger N returns IGAFD_ERR_ARG.  Every call on one
+ * GPU shares that accumulator, which keeps the last call's contents (each
+ * call clears what it uses first): calls that overlap on one GPU (other
+ * streams, other host threads) race.  The context's device must be current. */
+igafd_status igafd_features_noalloc(igafd_ctx* ctx, float* feat_dev);
+
 /* Training targets t_i = 1/2 log(P_ii / A_ii) (N floats, device). */
 igafd_status igafd_scaling_targets(igafd_ctx* ctx, float* t_dev);
 

@@ -6,7 +6,7 @@ The solver lives in the HIP library libigafd.so (C ABI in include/igafd.h);
 library; the first igafd_* call does, and fails loudly when it is not built.
 """
 from .binding import (IgafdError, Context, Mlp, igafd_apply_A, igafd_apply_precond, igafd_autotune,
-                      igafd_destroy, igafd_diagonals, igafd_features, igafd_get_adi, igafd_get_eigen,
+                      igafd_destroy, igafd_diagonals, igafd_features, igafd_features_noalloc, igafd_get_adi, igafd_get_eigen,
                       igafd_get_shape, igafd_last_error, igafd_load_vector, igafd_lshape_corner,
                       igafd_lshape_setup, igafd_mlp_create, igafd_mlp_destroy, igafd_mlp_fit_normalization,
                       igafd_mlp_forward, igafd_mlp_get_params, igafd_mlp_gradient, igafd_mlp_num_params,
@@ -16,7 +16,7 @@ from .binding import (IgafdError, Context, Mlp, igafd_apply_A, igafd_apply_preco
                       igafd_spectral_bounds, igafd_univariate, lib)
 
 __all__ = ["IgafdError", "Context", "Mlp", "igafd_apply_A", "igafd_apply_precond", "igafd_autotune",
-           "igafd_destroy", "igafd_diagonals", "igafd_features", "igafd_get_adi", "igafd_get_eigen",
+           "igafd_destroy", "igafd_diagonals", "igafd_features", "igafd_features_noalloc", "igafd_get_adi", "igafd_get_eigen",
            "igafd_get_shape", "igafd_last_error", "igafd_load_vector", "igafd_lshape_corner",
            "igafd_lshape_setup", "igafd_mlp_create", "igafd_mlp_destroy", "igafd_mlp_fit_normalization",
            "igafd_mlp_forward", "igafd_mlp_get_params", "igafd_mlp_gradient", "igafd_mlp_num_params",

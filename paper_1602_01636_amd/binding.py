@@ -83,6 +83,7 @@ _SIGNATURES = {
     "igafd_destroy": (None, [C.c_void_p]),
     "igafd_last_error": (C.c_char_p, []),
     "igafd_features": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "igafd_features_noalloc": (C.c_int, [C.c_void_p, C.c_void_p]),
     "igafd_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(igafd_solve_opts),
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
@@ -457,6 +458,11 @@ def igafd_destroy(ctx):
 def igafd_features(ctx: Context, feat):
     """Per-dof network inputs into feat (float32, N x 8)."""
     _check(lib().igafd_features(_h(ctx), _fptr(feat, ctx.N, "feat", 8)))
+
+
+def igafd_features_noalloc(ctx: Context, feat):
+    """igafd_features without any device allocation (static accumulator, N <= 2^20)."""
+    _check(lib().igafd_features_noalloc(_h(ctx), _fptr(feat, ctx.N, "feat", 8)))
 
 
 def igafd_scaling_targets(ctx: Context, t):

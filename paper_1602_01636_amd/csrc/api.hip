@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "internal.h"
 #include "reduce.h"
@@ -1320,6 +1321,74 @@ igafd_status igafd_features(igafd_ctx* c, float* feat) {
   if (is_lshape(c, "igafd_features")) return IGAFD_ERR_ARG;
   if (no_A(c, "igafd_features")) return IGAFD_ERR_ARG;
   return features(c, feat);
+}
+
+}  // extern "C"
+
+namespace igafd {
+namespace {
+// Accumulator of igafd_features_noalloc: 8 doubles per dof for N <= 2^20
+// (64 MiB), a file-scope device array that every GPU the library runs on
+// holds from module load until the process ends.  Host code never passes
+// `scratch` itself (on the host that name is only a stand-in): the device
+// address comes from hipGetSymbolAddress, looked up once per device.
+constexpr long long kScratchDofs = 1LL << 20;
+__device__ __align__(256) double scratch[8 * kScratchDofs];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device `dev` (the current device)
+igafd_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device ordinal out of range for the static accumulator");
+    return IGAFD_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    double* p = nullptr;
+    IGAFD_HIP_CHECK(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("hipGetSymbolAddress returned no address for the static accumulator");
+      return IGAFD_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return IGAFD_OK;
+}
+}  // namespace
+}  // namespace igafd
+
+extern "C" {
+
+igafd_status igafd_features_noalloc(igafd_ctx* c, float* feat) {
+  if (!c || !feat) {
+    set_error("null argument");
+    return IGAFD_ERR_ARG;
+  }
+  if (is_lshape(c, "igafd_features_noalloc")) return IGAFD_ERR_ARG;
+  if (no_A(c, "igafd_features_noalloc")) return IGAFD_ERR_ARG;
+  if (c->feat) {  // assembled with A at setup: a device copy
+    IGAFD_HIP_CHECK(
+        hipMemcpyAsync(feat, c->feat, sizeof(float) * 8 * (size_t)c->N, hipMemcpyDeviceToDevice, c->stream));
+    return IGAFD_OK;
+  }
+  if (c->N > kScratchDofs) {
+    set_error("igafd_features_noalloc: N = " + std::to_string(c->N) + " exceeds the static accumulator (" +
+              std::to_string(kScratchDofs) + " dofs); use igafd_features or set up with want_features");
+    return IGAFD_ERR_ARG;
+  }
+  int dev = -1;
+  IGAFD_HIP_CHECK(hipGetDevice(&dev));
+  if (dev != c->device) {
+    set_error("igafd_features_noalloc: the context's device must be current");
+    return IGAFD_ERR_ARG;
+  }
+  double* acc = nullptr;
+  IGAFD_TRY(scratch_address(dev, &acc));
+  return features_into(c, acc, feat);
 }
 
 igafd_status igafd_scaling_targets(igafd_ctx* c, float* t) {
