@@ -13,6 +13,7 @@
 // b - A x is evaluated in FP64 and the iteration restarts from it if it does
 // not meet the tolerance.  flexible = 1 uses the Polak-Ribiere beta
 // (r_{k+1}, z_{k+1} - z_k) / (r_k, z_k) for inexact (FP32/BF16) applies.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -723,7 +724,24 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
     }
     Sp[i] = use ? cs[i]->scaling : nullptr;
   }
-  const int nst = count < 8 ? count : 8;
+  int nst = 8;
+  if (const char* e = std::getenv("IGAFD_BATCH_STREAMS")) nst = std::max(1, std::min(32, std::atoi(e)));
+  nst = std::min(nst, count);
+  // streams by longest-processing-time first: problems in decreasing order of
+  // the bytes their A band moves per iteration, each to the least loaded stream
+  std::vector<int> slot(count, 0);
+  {
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)cs[i]->H * (double)cs[i]->Ns + 8.0 * (double)cs[i]->N; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<double> load(nst, 0.0);
+    for (int i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      slot[i] = k;
+      load[k] += work(i);
+    }
+  }
   std::vector<hipStream_t> pool(nst, nullptr), saved(count);
   std::vector<hipEvent_t> join(nst, nullptr);
   hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
@@ -782,9 +800,9 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   // streams of the contexts it takes over (uploads, load vectors, scalings)
   for (int i = 0; i < count; ++i) {
     IGAFD_BH(hipEventRecord(fork, saved[i]));
-    IGAFD_BH(hipStreamWaitEvent(pool[i % nst], fork, 0));
+    IGAFD_BH(hipStreamWaitEvent(pool[slot[i]], fork, 0));
   }
-  for (int i = 0; i < count; ++i) cs[i]->stream = pool[i % nst];
+  for (int i = 0; i < count; ++i) cs[i]->stream = pool[slot[i]];
   bound = true;
   auto sync_all = [&]() -> igafd_status {
     for (int k = 0; k < nst; ++k) IGAFD_HIP_CHECK(hipStreamSynchronize(pool[k]));

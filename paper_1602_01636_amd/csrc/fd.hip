@@ -17,10 +17,11 @@
 // matrices Wm (at most npad x npad, zero padded) stay in L1/L2.
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4),
-// BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x16_bf16), and split
-// BF16 (each FP32 operand as hi + lo BF16 parts, three BF16 MFMAs per
-// product).  r and s are FP64; intermediates are FP64 for FP64 and FP32
-// otherwise.
+// BF16 inputs with FP32 accumulation, and split BF16 (each FP32 operand as
+// hi + lo BF16 parts, three BF16 MFMAs per product).  The fused 3D passes use
+// gfx950's 32-deep v_mfma_f32_16x16x32_bf16; the generic per-strip products
+// (small 2D problems) the 16-deep v_mfma_f32_16x16x16_bf16.  r and s are
+// FP64; intermediates are FP64 for FP64 and FP32 otherwise.
 //
 // Fused epilogues: scaling by the eigenvalue sums, the diagonal S of the
 // scaled preconditioner S P^-1 S on input and output, and the partial sums of
@@ -37,6 +38,8 @@ namespace {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 __device__ inline short to_bf16(float f) {
   unsigned u = __float_as_uint(f);
@@ -61,6 +64,24 @@ __device__ inline f4_t mma_bf16x3(const s4_t& ahi, const s4_t& alo, const s4_t& 
   c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+}
+
+// gfx950's 32-deep BF16 MFMA: lane group g = l / 16 supplies 8 contracted
+// indices of its row (A) or column (B); which 8 does not matter as long as both
+// operands use the same ones.  The fused passes give it the two 16-deep groups
+// of a pipeline stage: values j = 0..3 of the first group, then of the second.
+__device__ inline s8_t cat8(const s4_t& lo, const s4_t& hi) {
+  return s8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+__device__ inline f4_t mma32(const s8_t& a, const s8_t& b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b), c, 0, 0,
+                                                 0);
+}
+// split BF16 with 32-deep operands (see mma_bf16x3)
+__device__ inline f4_t mma32_x3(const s8_t& ahi, const s8_t& alo, const s8_t& bhi, const s8_t& blo, f4_t c) {
+  c = mma32(alo, bhi, c);
+  c = mma32(ahi, blo, c);
+  return mma32(ahi, bhi, c);
 }
 
 // Operand layouts (checked on gfx950): A lane l holds row l%16, B lane l holds
@@ -375,7 +396,13 @@ __device__ inline int row_of(int grp, int r) {
   return Pr::ROW_STRIDE4 ? grp + 4 * r : 4 * grp + r;
 }
 
-constexpr int kSliceCols = 48;  // output columns (k1) per slice block
+// output columns (k1) per slice block: 16 NT with NT = 2 or 3 column tiles,
+// whichever pads the direction-1 tiles least (ties: 3, fewer blocks reload the
+// matrices): n = 129 (9 tiles) takes 48, n = 99 (7) and n = 114 (8) take 32
+__host__ __device__ constexpr int slice_nt(int n1) {
+  const int tiles = (n1 + 15) / 16;
+  return ((tiles + 2) / 3) * 3 <= ((tiles + 1) / 2) * 2 ? 3 : 2;
+}
 constexpr int kDir3Cols = 32;   // columns (i2, i1) per direction-3 block
 // waves per block of the fused passes; a direction of up to 160 (10 row
 // tiles of 16) gives each wave at most kMaxTilesPerWave tiles
@@ -452,42 +479,57 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
     }
   };
   auto compute = [&](int k0, int K, V (&a)[G][MT][4], V (&b)[G][NT][4]) {
+    if constexpr (Pr::KPL != 1) {
+      // BF16 and split BF16: both 16-deep groups of the stage in one 32-deep
+      // MFMA (a second group past K was loaded as zeros)
+      static_assert(G == 2, "32-deep BF16 products take two 16-deep groups");
+      auto bf4 = [](const V (&v)[4]) { return s4_t{to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3])}; };
+      if constexpr (Pr::SPLIT) {
+        s8_t pa[MT], la[MT], pb[NT], lb[NT];
 #pragma unroll
-    for (int u = 0; u < G; ++u) {
-      if (k0 + 16 * u >= K) break;
-      if constexpr (Pr::KPL == 1) {
+        for (int m = 0; m < MT; ++m) {
+          s4_t h0, l0, h1, l1;
+          split4(a[0][m], h0, l0);
+          split4(a[1][m], h1, l1);
+          pa[m] = cat8(h0, h1);
+          la[m] = cat8(l0, l1);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          s4_t h0, l0, h1, l1;
+          split4(b[0][t], h0, l0);
+          split4(b[1][t], h1, l1);
+          pb[t] = cat8(h0, h1);
+          lb[t] = cat8(l0, l1);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (wave + kFusedWaves * m < mtiles) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mma32_x3(pa[m], la[m], pb[t], lb[t], acc[m][t]);
+          }
+      } else {
+        s8_t pa[MT], pb[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) pa[m] = cat8(bf4(a[0][m]), bf4(a[1][m]));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pb[t] = cat8(bf4(b[0][t]), bf4(b[1][t]));
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (wave + kFusedWaves * m < mtiles) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mma32(pa[m], pb[t], acc[m][t]);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (k0 + 16 * u >= K) break;
 #pragma unroll
         for (int m = 0; m < MT; ++m)
           if (wave + kFusedWaves * m < mtiles) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) grp_mma<Pr>(a[u][m], b[u][t], acc[m][t]);
-          }
-      } else if constexpr (Pr::SPLIT) {
-        s4_t pa[MT], la[MT], pb[NT], lb[NT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) split4(a[u][m], pa[m], la[m]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) split4(b[u][t], pb[t], lb[t]);
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-          if (wave + kFusedWaves * m < mtiles) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = mma_bf16x3(pa[m], la[m], pb[t], lb[t], acc[m][t]);
-          }
-      } else {
-        s4_t pa[MT], pb[NT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-          pa[m] = s4_t{to_bf16(a[u][m][0]), to_bf16(a[u][m][1]), to_bf16(a[u][m][2]), to_bf16(a[u][m][3])};
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          pb[t] = s4_t{to_bf16(b[u][t][0]), to_bf16(b[u][t][1]), to_bf16(b[u][t][2]), to_bf16(b[u][t][3])};
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-          if (wave + kFusedWaves * m < mtiles) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[m], pb[t], acc[m][t], 0, 0, 0);
           }
       }
     }
@@ -535,15 +577,15 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
 }
 
 // Pass A / C: Out[i2][k1] = sum_j2 V2[i2][j2] sum_i1 X[j2][i1] V1[k1][i1] for
-// slice blockIdx.y and output columns k1 in [blockIdx.x * 48, +48).  X, Out:
+// slice blockIdx.y and output columns k1 in [blockIdx.x * 16 NT, +16 NT).  X, Out:
 // slice-contiguous (n2 x n1); V1, V2 row-major, zero padded to npad1, npad2.
-template <class Pr, typename Tin, typename Tout, typename Tw, typename Tmid>
+template <class Pr, int NT, typename Tin, typename Tout, typename Tw, typename Tmid>
 __global__ __launch_bounds__(kFusedThreads) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
                                                   const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
                                                   int npad1, int npad2, Epi ep) {
   using acc_t = typename Pr::acc;
   using V = typename Grp<Pr>::V;
-  constexpr int NT = kSliceCols / 16;
+  constexpr int kSliceCols = 16 * NT;
   if (ep.flag && *ep.flag) return;
   extern __shared__ char smem_raw[];
   Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
@@ -699,7 +741,10 @@ bool fused_ok(const igafd_ctx* c) {
   return c->dim == 3 && c->n[0] <= 160 && c->n[1] <= 160 && c->n[2] <= 160;
 }
 
-int slice_blocks(const igafd_ctx* c) { return ((c->n[0] + kSliceCols - 1) / kSliceCols) * c->n[2]; }
+int slice_blocks(const igafd_ctx* c) {
+  const int cols = 16 * slice_nt(c->n[0]);
+  return ((c->n[0] + cols - 1) / cols) * c->n[2];
+}
 
 template <class Pr, typename T, typename Tw>
 igafd_status apply_fused(igafd_ctx* c, const Tw* const* Wf, const Tw* const* Wb, const double* r, double* s,
@@ -730,18 +775,27 @@ igafd_status apply_fused(igafd_ctx* c, const Tw* const* Wf, const Tw* const* Wb,
   e_lam.lamK = d[2].lam;
   e_lam.lam1 = d[0].lam;
   e_lam.lam2 = d[1].lam;
-  const dim3 gs((unsigned)((n1 + kSliceCols - 1) / kSliceCols), (unsigned)n3);
-  const size_t lds_s = sizeof(T) * (size_t)kSliceCols * lds_ld<T>((n2 + 15) / 16);
+  const int nt = slice_nt(n1), cols = 16 * nt;
+  const dim3 gs((unsigned)((n1 + cols - 1) / cols), (unsigned)n3);
+  const size_t lds_s = sizeof(T) * (size_t)cols * lds_ld<T>((n2 + 15) / 16);
   const size_t lds_3 = sizeof(T) * (size_t)kDir3Cols * lds_ld<T>((n3 + 15) / 16);
   const int C = n1 * n2;
-  hipLaunchKernelGGL((k_slice<Pr, double, T, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, r, b0, Wf[0], Wf[1], n1, n2,
-                     d[0].npad, d[1].npad, e_in);
+  if (nt == 3)
+    hipLaunchKernelGGL((k_slice<Pr, 3, double, T, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, r, b0, Wf[0], Wf[1], n1,
+                       n2, d[0].npad, d[1].npad, e_in);
+  else
+    hipLaunchKernelGGL((k_slice<Pr, 2, double, T, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, r, b0, Wf[0], Wf[1], n1,
+                       n2, d[0].npad, d[1].npad, e_in);
   IGAFD_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL((k_dir3<Pr, Tw, T>), dim3((unsigned)((C + kDir3Cols - 1) / kDir3Cols)), dim3(kFusedThreads), lds_3, st,
                      b0, b1, Wf[2], Wb[2], n3, C, d[2].npad, e_lam);
   IGAFD_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_slice<Pr, T, double, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, b1, s, Wb[0], Wb[1], n1, n2,
-                     d[0].npad, d[1].npad, e_out);
+  if (nt == 3)
+    hipLaunchKernelGGL((k_slice<Pr, 3, T, double, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, b1, s, Wb[0], Wb[1], n1,
+                       n2, d[0].npad, d[1].npad, e_out);
+  else
+    hipLaunchKernelGGL((k_slice<Pr, 2, T, double, Tw, T>), gs, dim3(kFusedThreads), lds_s, st, b1, s, Wb[0], Wb[1], n1,
+                       n2, d[0].npad, d[1].npad, e_out);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
