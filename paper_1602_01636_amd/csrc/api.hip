@@ -836,6 +836,13 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   }
   const bool use_graph = std::getenv("IGAFD_NO_GRAPH") == nullptr;
   int captured_for = -1;
+  // A graph captured for a set of running problems stays valid after some of
+  // them converge (their kernels turn into no-ops on the device stop flag);
+  // it is captured again only when the running count has fallen below
+  // `keep` times the captured one, trading no-op launches against capture
+  // and instantiation (a few ms for thousands of nodes).
+  double keep = 0.75;
+  if (const char* e = std::getenv("IGAFD_BATCH_RECAPTURE")) keep = std::atof(e);
   while (true) {
     int nrun = 0;
     for (int i = 0; i < count; ++i) nrun += running[i];
@@ -849,7 +856,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
       return IGAFD_OK;
     };
     if (use_graph) {
-      if (captured_for != nrun) {  // (re)capture the chunk for the running set
+      if (captured_for < 0 || nrun < keep * captured_for) {  // (re)capture the chunk for the running set
         if (exec) IGAFD_BH(hipGraphExecDestroy(exec));
         if (graph) IGAFD_BH(hipGraphDestroy(graph));
         exec = nullptr;
