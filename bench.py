@@ -411,15 +411,22 @@ def run_learned(args, api, torch, synth):
     log(f"trained on {total} dofs of {args.train} problems in {t_train:.1f}s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     E, p = args.elements or 112, args.degree or 4
     prob = synth.learned_eval_problem(E=E, p=p)
-    # the setup's cost of the features: the same setup without and with them
-    t0 = time.perf_counter()
-    api.igafd_setup(prob).close()
-    torch.cuda.synchronize()
-    t_setup_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ctx = api.igafd_setup(prob, features=True)
-    torch.cuda.synchronize()
-    t_setup_feat = time.perf_counter() - t0
+    # the setup's cost of the features: the same setup without and with them,
+    # alternating, three times each (medians; one setup varies by a few ms)
+    t_plain, t_feat = [], []
+    ctx = None
+    for rep in range(3):
+        t0 = time.perf_counter()
+        api.igafd_setup(prob).close()
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+        if ctx is not None:
+            ctx.close()
+        t0 = time.perf_counter()
+        ctx = api.igafd_setup(prob, features=True)
+        torch.cuda.synchronize()
+        t_feat.append(time.perf_counter() - t0)
+    t_setup_plain, t_setup_feat = float(np.median(t_plain)), float(np.median(t_feat))
     b = rhs(api, torch, synth, ctx)
     u = torch.zeros_like(b)
     res = {}
@@ -838,7 +845,10 @@ def main():
         out["learned_scaling"] = {
             "config": ln["config"], "variants": lv, "train_s": ln["train_s"], "train_dofs": ln["train_dofs"],
             "loss_first_last": ln["loss_first_last"], "saving_per_solve_s": saving,
-            "prediction_cost_s": cost, "pays_off_first_solve": bool(cost < saving)}
+            "prediction_cost_s": cost, "pays_off_first_solve": bool(cost < saving),
+            # solves of one setup (right-hand sides) after which the features and
+            # the prediction have paid for themselves
+            "pays_off_after_solves": (int(np.ceil(cost / saving)) if saving > 0 else None)}
     print(json.dumps(out), flush=True)
 
 

@@ -108,31 +108,34 @@ __host__ __device__ constexpr int sym_index(int a, int b) {
 }
 
 // Per-dof statistics of the learned scaling, one element's share: for the
-// four channels ch0..ch0+3 and every local function a = (a1, a2, a3) of the
-// element, sum_t B_a(t) v(ch, t) over the element's Gauss points t, where
+// NCH channels ch0..ch0+NCH-1 and every local function a = (a1, a2, a3) of
+// the element, sum_t B_a(t) v(ch, t) over the element's Gauss points t, where
 // v(ch, t) = w_t G_ch(t) (ch < 6: the entries 11, 22, 33, 12, 13, 23 of
-// G = |det J| J^-1 J^-T), w_t kappa(t) (ch = 6) or w_t (ch = 7).  The sum is
-// taken one direction at a time (sum factorisation: t1, then t2, then t3)
-// and added into acc[8 row + ch] for the functions that are dofs; the
-// element's colour class guarantees no other block adds to those rows.  F1
-// (4 L Q Q3 doubles) and F2 (4 L L Q3) are LDS scratch.
-template <int D, int P, typename V>
-__device__ void feature_sums4(int ch0, V v, const double (*sV)[P + 1][P + 1], const int* first, const Tables& T,
-                              double* F1, double* F2, double* __restrict__ acc) {
+// G = |det J| J^-1 J^-T), w_t kappa(t) (ch = 6) or w_t (ch = 7), given in
+// vals[ch - ch0][t].  The sum is taken one direction at a time (sum
+// factorisation: t1, then t2, then t3) and added into acc[8 row + ch] for the
+// functions that are dofs; the element's colour class guarantees no other
+// block adds to those rows.  F1 (NCH L Q Q3 doubles) and F2 (NCH L L Q3) are
+// LDS scratch; vals may share F2's storage (it is last read before F2 is
+// written).
+template <int D, int P, int NCH>
+__device__ void feature_sums(int ch0, const double* vals, const double (*sV)[P + 1][P + 1], const int* first,
+                             const Tables& T, double* F1, double* F2, double* __restrict__ acc) {
   constexpr int Q = P + 1, L = P + 1;
   constexpr int Q3 = (D == 3) ? Q : 1;
   constexpr int L3 = (D == 3) ? L : 1;
+  constexpr int NQ = Q * Q * Q3;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < 4 * L * Q * Q3; idx += kBlock) {  // F1[c][t2 + Q t3][a1]
+  for (int idx = tid; idx < NCH * L * Q * Q3; idx += kBlock) {  // F1[c][t2 + Q t3][a1]
     const int c = idx / (L * Q * Q3), r = idx % (L * Q * Q3);
     const int a1 = r % L, t23 = r / L;
     double s = 0.0;
 #pragma unroll
-    for (int t1 = 0; t1 < Q; ++t1) s += sV[0][t1][a1] * v(ch0 + c, t1 + Q * t23);
+    for (int t1 = 0; t1 < Q; ++t1) s += sV[0][t1][a1] * vals[c * NQ + t1 + Q * t23];
     F1[idx] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < 4 * L * L * Q3; idx += kBlock) {  // F2[c][t3][a2][a1]
+  for (int idx = tid; idx < NCH * L * L * Q3; idx += kBlock) {  // F2[c][t3][a2][a1]
     const int c = idx / (L * L * Q3), r = idx % (L * L * Q3);
     const int a1 = r % L, a2 = (r / L) % L, t3 = r / (L * L);
     double s = 0.0;
@@ -141,7 +144,17 @@ __device__ void feature_sums4(int ch0, V v, const double (*sV)[P + 1][P + 1], co
     F2[idx] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < 4 * L * L * L3; idx += kBlock) {
+  // the sums of a thread first, then all their loads before any store
+  // (distinct rows and channels)
+  constexpr int ITEMS = NCH * L * L * L3, PER = (ITEMS + kBlock - 1) / kBlock;
+  double sv[PER];
+  long long off[PER];  // -1: not a dof
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    off[k] = -1;
+    sv[k] = 0.0;
+    const int idx = tid + k * kBlock;
+    if (idx >= ITEMS) continue;
     const int c = idx / (L * L * L3), r = idx % (L * L * L3);
     const int a1 = r % L, a2 = (r / L) % L, a3 = r / (L * L);
     const int r1 = first[0] + a1 - 1, r2 = first[1] + a2 - 1, r3 = (D == 3) ? first[2] + a3 - 1 : 0;
@@ -149,8 +162,15 @@ __device__ void feature_sums4(int ch0, V v, const double (*sV)[P + 1][P + 1], co
     double s = 0.0;
 #pragma unroll
     for (int t3 = 0; t3 < Q3; ++t3) s += sV[2][t3][a3] * F2[c * (L * L * Q3) + (t3 * L + a2) * L + a1];
-    acc[8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)) + ch0 + c] += s;
+    off[k] = 8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)) + ch0 + c;
+    sv[k] = s;
   }
+  double old[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) old[k] = off[k] >= 0 ? acc[off[k]] : 0.0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (off[k] >= 0) acc[off[k]] = old[k] + sv[k];
   __syncthreads();
 }
 
@@ -179,8 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
   __shared__ int sFirst[3];
   // features: kappa and the weight per point, F2 of the contraction (F1 lives in sG)
   __shared__ double sKap[FEAT ? NQ : 1], sW[FEAT ? NQ : 1];
-  __shared__ double sF2[FEAT ? 4 * L * L * Q3 : 1];
-  static_assert(!FEAT || NAB * L * L * Q >= 4 * L * Q * Q3, "feature scratch F1 must fit in sG");
+  // feature channels per pass: all eight, or four at a time from p = 5 on
+  // (eight made the LDS of p = 5 allow three blocks per CU instead of four)
+  constexpr int NCH = (P >= 5) ? 4 : 8;
+  __shared__ double sF2[FEAT ? NCH * L * L * Q3 : 1];  // the channel values, then F2
+  static_assert(!FEAT || NAB * L * L * Q >= NCH * L * Q * Q3, "feature scratch F1 must fit in sG");
+  static_assert(!FEAT || L * L * Q3 >= NQ, "channel values must fit in sF2");
 
   int bid = blockIdx.x;
   const int j1 = bid % m1;
@@ -229,16 +253,26 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, doubl
   }
   __syncthreads();
   if (FEAT) {
-    // w G_ab = C_ab / kappa; the channel order is (11, 22, 33, 12, 13, 23, kappa, 1)
-    auto v = [&](int ch, int t) -> double {
-      if (ch == 6) return sW[t] * sKap[t];
-      if (ch == 7) return sW[t];
-      constexpr int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-      if (ia[ch] >= D || ib[ch] >= D) return 0.0;
-      return sC[sym_index<D>(ia[ch], ib[ch])][t] / sKap[t];
-    };
-    feature_sums4<D, P>(0, v, sV, sFirst, T, &sG[0][0][0], sF2, acc);
-    feature_sums4<D, P>(4, v, sV, sFirst, T, &sG[0][0][0], sF2, acc);
+    // the channel values at the Gauss points, once each per pass: w G_ab =
+    // C_ab / kappa; the channel order is (11, 22, 33, 12, 13, 23, kappa, 1)
+    for (int ch0 = 0; ch0 < 8; ch0 += NCH) {
+      for (int idx = tid; idx < NCH * NQ; idx += kBlock) {
+        const int ch = ch0 + idx / NQ, t = idx % NQ;
+        constexpr int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+        double v;
+        if (ch == 6)
+          v = sW[t] * sKap[t];
+        else if (ch == 7)
+          v = sW[t];
+        else if (ia[ch] >= D || ib[ch] >= D)
+          v = 0.0;
+        else
+          v = sC[sym_index<D>(ia[ch], ib[ch])][t] / sKap[t];
+        sF2[idx] = v;
+      }
+      __syncthreads();
+      feature_sums<D, P, NCH>(ch0, sF2, sV, sFirst, T, &sG[0][0][0], sF2, acc);
+    }
   }
 
   for (int a3 = 0; a3 < L3; ++a3) {
@@ -382,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_load(Tables T, GeomDesc g, RhsDesc r
 
 // Per-dof geometry/coefficient statistics for the learned scaling, without
 // assembling A: the same Gauss-point values as k_assemble's feature channels
-// (w G's six entries, w kappa, w), summed into acc by feature_sums4.
+// (w G's six entries, w kappa, w), summed into acc by feature_sums.
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, double* __restrict__ acc, int c1, int c2,
                                                      int c3, int m1, int m2) {
@@ -391,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, doubl
   constexpr int NQ = Q * Q * Q3;
   __shared__ double sf[8][NQ];
   __shared__ double sV[3][Q][L];
-  __shared__ double sF1[4 * L * Q * Q3], sF2[4 * L * L * Q3];
+  __shared__ double sF1[8 * L * Q * Q3], sF2[8 * L * L * Q3];
   __shared__ int sFirst[3];
   int bid = blockIdx.x;
   const int j1 = bid % m1;
@@ -433,9 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_features(Tables T, GeomDesc g, doubl
     sf[7][t] = w;
   }
   __syncthreads();
-  auto v = [&](int ch, int t) -> double { return sf[ch][t]; };
-  feature_sums4<D, P>(0, v, sV, sFirst, T, sF1, sF2, acc);
-  feature_sums4<D, P>(4, v, sV, sFirst, T, sF1, sF2, acc);
+  feature_sums<D, P, 8>(0, &sf[0][0], sV, sFirst, T, sF1, sF2, acc);
 }
 
 // Extreme eigenvalues of a symmetric positive definite 2x2 / 3x3 matrix.
