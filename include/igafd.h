@@ -206,12 +206,17 @@ typedef struct {
 igafd_status igafd_solve(igafd_ctx* ctx, const double* b_dev, double* u_dev,
                          const igafd_solve_opts* opts, igafd_solve_info* info);
 
-/* Independent problems solved together (the batch workload): contexts are
- * bound to a pool of streams for the duration of the call; each chunk of
- * check_every iterations of all running problems is captured into one HIP
- * graph and replayed until every problem has converged (re-captured when
- * problems finish).  b[i], u[i]: device vectors of ctxs[i]; x0 = 0.
- * infos (count entries) and wall_ms (device time of the CG loops) optional. */
+/* Independent problems solved together (the batch workload).  When every
+ * problem is 3D with the fused FD passes, each step of a CG iteration is one
+ * grouped launch over all running problems (device job tables allocated for
+ * the call), on one stream that the contexts share for the duration of the
+ * call; otherwise the contexts are bound to a pool of streams.  Each chunk of
+ * check_every iterations (rounded up to even) is captured into one HIP graph
+ * and replayed until every problem has converged (re-captured when problems
+ * finish).  Every problem's iterates are bitwise those of its own igafd_solve.
+ * b[i], u[i]: device vectors of ctxs[i]; x0 = 0.  infos (count entries) and
+ * wall_ms (device time of the CG loops) optional.  Environment (testing):
+ * IGAFD_BATCH_GROUPED=0 forces the stream pool. */
 igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double* const* b, double* const* u,
                                  const igafd_solve_opts* opts, igafd_solve_info* infos, double* wall_ms);
 

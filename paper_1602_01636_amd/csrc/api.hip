@@ -71,9 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ b, c
 // sums are pending) in a fixed order, then the scalar step of CG.
 constexpr int kReduceBlock = 1024;  // one wide block: a few independent loads per thread
 
-__global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restrict__ partial, int count, int two,
-                                                         int which, SolverState* __restrict__ s,
-                                                         double* __restrict__ hist) {
+__device__ __forceinline__ void reduce_body(const double* __restrict__ partial, int count, int two, int which,
+                                            SolverState* __restrict__ s, double* __restrict__ hist) {
   if (which != RED_BB_RR && which != RED_RHO0 && which != RED_TRUE && s->flag != FLAG_RUNNING) return;
   double a = 0.0, b = 0.0;
 #pragma unroll 4
@@ -130,14 +129,33 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restric
   }
 }
 
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(const double* __restrict__ partial, int count, int two,
+                                                         int which, SolverState* __restrict__ s,
+                                                         double* __restrict__ hist) {
+  reduce_body(partial, count, two, which, s, hist);
+}
+
+// Grouped forms of the CG kernels (batched solves): one launch runs the step
+// for several problems; job j owns blocks [start[j], start[j+1]) (one block
+// per job for the reductions).
+struct ReduceJob {
+  const double* partial;
+  int count, two;
+  SolverState* s;
+};
+
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_g(const ReduceJob* __restrict__ jobs, int which) {
+  const ReduceJob& t = jobs[blockIdx.x];
+  reduce_body(t.partial, t.count, t.two, which, t.s, nullptr);
+}
+
 // x += alpha p; r -= alpha q; partials (r, r) and (r, z_old).
-__global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                      const double* __restrict__ p, const double* __restrict__ q,
-                                                      const double* __restrict__ zold, const SolverState* __restrict__ s,
-                                                      long long N, double* __restrict__ partial) {
-  if (s->flag != FLAG_RUNNING) return;
+__device__ __forceinline__ void update_xr_body(double* __restrict__ x, double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               const double* __restrict__ zold, const SolverState* __restrict__ s,
+                                               long long N, double* __restrict__ partial, int bx, int gx) {
   const double alpha = s->alpha;
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long i = (long long)bx * kBlock + threadIdx.x;
   double rr = 0.0, rz = 0.0;
   if (i < N) {
     x[i] = fma(alpha, p[i], x[i]);
@@ -148,9 +166,37 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, do
   }
   block_sum2(rr, rz);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = rr;
-    partial[gridDim.x + blockIdx.x] = rz;
+    partial[bx] = rr;
+    partial[gx + bx] = rz;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      const double* __restrict__ zold, const SolverState* __restrict__ s,
+                                                      long long N, double* __restrict__ partial) {
+  if (s->flag != FLAG_RUNNING) return;
+  update_xr_body(x, r, p, q, zold, s, N, partial, (int)blockIdx.x, (int)gridDim.x);
+}
+
+struct UpdateXrJob {
+  double* x;
+  double* r;
+  const double* p;
+  const double* q;
+  const double* zold;
+  const SolverState* s;
+  long long N;
+  double* partial;
+  int gx;
+};
+
+__global__ __launch_bounds__(kBlock) void k_update_xr_g(const UpdateXrJob* __restrict__ jobs,
+                                                        const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const UpdateXrJob& t = jobs[j];
+  if (t.s->flag != FLAG_RUNNING) return;
+  update_xr_body(t.x, t.r, t.p, t.q, t.zold, t.s, t.N, t.partial, (int)blockIdx.x - start[j], t.gx);
 }
 
 // p = z + beta p (beta = 0 on the first direction: p = z).
@@ -160,6 +206,29 @@ __global__ __launch_bounds__(kBlock) void k_update_p(double* __restrict__ p, con
   const double beta = first ? 0.0 : s->beta;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (i < N) p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+}
+
+struct UpdatePJob {
+  double* p;
+  const double* z;
+  const SolverState* s;
+  long long N;
+};
+
+__global__ __launch_bounds__(kBlock) void k_update_p_g(const UpdatePJob* __restrict__ jobs,
+                                                       const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const UpdatePJob& t = jobs[j];
+  if (t.s->flag != FLAG_RUNNING) return;
+  const double beta = t.s->beta;
+  const long long i = (long long)((int)blockIdx.x - start[j]) * kBlock + threadIdx.x;
+  if (i < t.N) t.p[i] = fma(beta, t.p[i], t.z[i]);
+}
+
+// flags[j] = the CG flag of problem j (one copy to the host per check)
+__global__ void k_gather_flags(SolverState* const* __restrict__ states, int n, int* __restrict__ flags) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j < n) flags[j] = states[j]->flag;
 }
 
 // r = b - q and its squared norm (true residual).
@@ -694,12 +763,168 @@ igafd_status solve_impl(igafd_ctx* c, const double* b, double* x, const igafd_so
   return (igafd_status)status;
 }
 
-// Several independent problems solved together: each context is bound to
-// one stream of a small pool, every chunk of iterations of all running
-// problems is captured once into a HIP graph (fork/join over the pool) and
-// replayed until all have converged; the graph is rebuilt when problems
-// finish.  Every kernel of a converged problem is a no-op (device stop flag).
-// Problems that fail the FP64 true-residual check continue alone.
+}  // namespace
+
+size_t GroupArena::push(const void* p, size_t bytes) {
+  const size_t off = (host.size() + 63) / 64 * 64;
+  host.resize(off + bytes);
+  if (bytes) std::memcpy(host.data() + off, p, bytes);
+  return off;
+}
+
+igafd_status GroupArena::upload(hipStream_t st) {
+  if (host.empty()) return IGAFD_OK;
+  if (!dev || cap < host.size()) {
+    if (dev) IGAFD_HIP_CHECK(hipFree(dev));
+    dev = nullptr;
+    cap = 0;
+    IGAFD_HIP_CHECK(hipMalloc((void**)&dev, host.size()));
+    cap = host.size();
+  }
+  IGAFD_HIP_CHECK(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  IGAFD_HIP_CHECK(hipStreamSynchronize(st));
+  return IGAFD_OK;
+}
+
+void GroupArena::release() {
+  if (dev) (void)hipFree(dev);
+  dev = nullptr;
+  cap = 0;
+  host.clear();
+}
+
+namespace {
+
+// The launches of one CG iteration (the steps of enqueue_iteration) for the
+// problems `run`, each step one grouped launch over all of them (the tiled A
+// product and the slice passes: one per kernel shape).  steps[0]: z[i] holds
+// the current z (the flexible form's z_old of this iteration), the new z goes
+// to zold[i]; steps[1]: the roles swapped (the next iteration).  *flags_off:
+// the table of state pointers for k_gather_flags.
+igafd_status build_grouped(GroupArena& a, std::vector<GroupStep> (&steps)[2], size_t* flags_off,
+                           const std::vector<int>& run, igafd_ctx* const* cs, double* const* xs, int prec,
+                           int flexible, const std::vector<const double*>& Sp, const std::vector<double*>& z,
+                           const std::vector<double*>& zold) {
+  a.host.clear();
+  steps[0].clear();
+  steps[1].clear();
+  const int n = (int)run.size();
+  std::vector<igafd_ctx*> cc;
+  std::vector<const double*> pv, rv, S;
+  std::vector<double*> q, part;
+  std::vector<SolverState*> states;
+  for (int i : run) {
+    igafd_ctx* c = cs[i];
+    IGAFD_TRY(check_partials(c, (long long)vblocks(c)));
+    cc.push_back(c);
+    pv.push_back(c->pv);
+    rv.push_back(c->r);
+    S.push_back(Sp[i]);
+    q.push_back(c->q);
+    part.push_back(c->partial);
+    states.push_back(c->state);
+  }
+  *flags_off = a.push(states.data(), sizeof(SolverState*) * states.size());
+  auto red_table = [&](int which, int two) -> long long {
+    std::vector<ReduceJob> jobs;
+    for (igafd_ctx* c : cc) {
+      const int count = which == RED_PQ ? spmv_blocks(c) : which == RED_RR ? (int)vblocks(c) : fd_dot_blocks(c, prec);
+      if (count > c->npartial) return -1;
+      jobs.push_back(ReduceJob{c->partial, count, two, c->state});
+    }
+    return (long long)a.push(jobs.data(), sizeof(ReduceJob) * jobs.size());
+  };
+  const long long red_pq = red_table(RED_PQ, 0), red_rr = red_table(RED_RR, flexible), red_rz = red_table(RED_RZ, 0);
+  if (red_pq < 0 || red_rr < 0 || red_rz < 0) {
+    set_error("internal: reduction count larger than the partial-sum buffer");
+    return IGAFD_ERR_ARG;
+  }
+  auto reduce_step = [&a, n](long long off, int which) -> GroupStep {
+    return [&a, n, off, which](hipStream_t st) -> igafd_status {
+      hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)n), dim3(kReduceBlock), 0, st, a.at<ReduceJob>((size_t)off),
+                         which);
+      IGAFD_HIP_CHECK(hipGetLastError());
+      return IGAFD_OK;
+    };
+  };
+  for (int par = 0; par < 2; ++par) {
+    std::vector<double*> za, zb;
+    for (int i : run) {
+      za.push_back(par ? zold[i] : z[i]);
+      zb.push_back(par ? z[i] : zold[i]);
+    }
+    std::vector<GroupStep>& st = steps[par];
+    // q = A p, (p, q)
+    IGAFD_TRY(spmv_grouped(a, st, cc, pv, q, part));
+    st.push_back(reduce_step(red_pq, RED_PQ));
+    // x += alpha p, r -= alpha q, (r, r) [, (r, z_old)]
+    {
+      std::vector<UpdateXrJob> jobs;
+      std::vector<int> start(1, 0);
+      for (int k = 0; k < n; ++k) {
+        igafd_ctx* c = cc[k];
+        const int vb = (int)vblocks(c);
+        jobs.push_back(UpdateXrJob{xs[run[k]], c->r, c->pv, c->q, flexible ? za[k] : nullptr, c->state, c->N,
+                                   c->partial, vb});
+        start.push_back(start.back() + vb);
+      }
+      const size_t oj = a.push(jobs.data(), sizeof(UpdateXrJob) * jobs.size());
+      const size_t os = a.push(start.data(), sizeof(int) * start.size());
+      const int blocks = start.back();
+      st.push_back([&a, oj, os, n, blocks](hipStream_t s0) -> igafd_status {
+        hipLaunchKernelGGL(k_update_xr_g, dim3((unsigned)blocks), dim3(kBlock), 0, s0, a.at<UpdateXrJob>(oj),
+                           a.at<int>(os), n);
+        IGAFD_HIP_CHECK(hipGetLastError());
+        return IGAFD_OK;
+      });
+    }
+    st.push_back(reduce_step(red_rr, RED_RR));
+    // z = M r, (r, z) -> beta
+    std::vector<double*> zbo(zb.begin(), zb.end());
+    IGAFD_TRY(fd_grouped(a, st, cc, prec, rv, zbo, S, part));
+    st.push_back(reduce_step(red_rz, RED_RZ));
+    // p = z + beta p
+    {
+      std::vector<UpdatePJob> jobs;
+      std::vector<int> start(1, 0);
+      for (int k = 0; k < n; ++k) {
+        igafd_ctx* c = cc[k];
+        jobs.push_back(UpdatePJob{c->pv, zb[k], c->state, c->N});
+        start.push_back(start.back() + (int)vblocks(c));
+      }
+      const size_t oj = a.push(jobs.data(), sizeof(UpdatePJob) * jobs.size());
+      const size_t os = a.push(start.data(), sizeof(int) * start.size());
+      const int blocks = start.back();
+      st.push_back([&a, oj, os, n, blocks](hipStream_t s0) -> igafd_status {
+        hipLaunchKernelGGL(k_update_p_g, dim3((unsigned)blocks), dim3(kBlock), 0, s0, a.at<UpdatePJob>(oj),
+                           a.at<int>(os), n);
+        IGAFD_HIP_CHECK(hipGetLastError());
+        return IGAFD_OK;
+      });
+    }
+  }
+  return IGAFD_OK;
+}
+
+bool batch_groupable(igafd_ctx* const* cs, int count, int prec) {
+  if (const char* e = std::getenv("IGAFD_BATCH_GROUPED"))
+    if (std::atoi(e) == 0) return false;
+  for (int i = 0; i < count; ++i)
+    if (!spmv_groupable(cs[i]) || !fd_groupable(cs[i], prec)) return false;
+  return true;
+}
+
+// Several independent problems solved together.  When every problem is 3D
+// with the fused FD passes, each step of a CG iteration is one grouped launch
+// over all running problems (per kernel shape for the A product and the slice
+// passes), from job tables built on the host: a chunk of iterations is
+// captured once into a HIP graph on one stream and replayed.  Otherwise each
+// context is bound to one stream of a small pool and the chunk is captured
+// with fork/join over the pool.  Either way the graph is rebuilt when the
+// running set shrinks enough, every kernel of a converged problem is a no-op
+// (device stop flag), the per-problem arithmetic is that of a single solve
+// (bitwise the same iterates), and problems that fail the FP64 true-residual
+// check continue alone.
 igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* const* bs, double* const* xs,
                                 const igafd_solve_opts* o, igafd_solve_info* infos, double* wall_ms) {
   for (int i = 0; i < count; ++i) {
@@ -724,9 +949,13 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
     }
     Sp[i] = use ? cs[i]->scaling : nullptr;
   }
+  // every problem on the tiled A product and the fused FD passes: one stream,
+  // each step of an iteration one grouped launch over all running problems;
+  // otherwise a pool of streams, one problem's launches after another's
+  const bool grouped = batch_groupable(cs, count, o->precision);
   int nst = 8;
   if (const char* e = std::getenv("IGAFD_BATCH_STREAMS")) nst = std::max(1, std::min(32, std::atoi(e)));
-  nst = std::min(nst, count);
+  nst = grouped ? 1 : std::min(nst, count);
   // streams by longest-processing-time first: problems in decreasing order of
   // the bytes their A band moves per iteration, each to the least loaded stream
   std::vector<int> slot(count, 0);
@@ -747,6 +976,8 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  GroupArena arena;       // job tables of the grouped launches
+  int* dflags = nullptr;  // the captured problems' CG flags, gathered per check
   igafd_status st = IGAFD_OK;
   std::vector<double*> z(count), zold(count);
   std::vector<char> running(count, 0);
@@ -754,6 +985,9 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (pool[0]) (void)hipStreamSynchronize(pool[0]);
+    arena.release();
+    if (dflags) (void)hipFree(dflags);
     // the callers' streams continue after everything the pool ran
     for (int k = 0; k < nst; ++k)
       if (pool[k] && join[k] && hipEventRecord(join[k], pool[k]) == hipSuccess)
@@ -836,14 +1070,73 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   }
   const bool use_graph = std::getenv("IGAFD_NO_GRAPH") == nullptr;
   int captured_for = -1;
+  double keep = 0.75;
+  if (const char* e = std::getenv("IGAFD_BATCH_RECAPTURE")) keep = std::atof(e);
+  if (grouped) {
+    // the steps of `chunk` iterations (even: z / z_old return to their roles)
+    // for the running set, captured once and replayed until the running count
+    // falls below `keep` times the captured one
+    std::vector<GroupStep> steps[2];
+    std::vector<int> run, cap_run;
+    std::vector<int> hflags(count, 0);
+    size_t flags_off = 0;
+    IGAFD_BH(hipMalloc((void**)&dflags, sizeof(int) * count));
+    const hipStream_t gs = pool[0];
+    auto enqueue = [&]() -> igafd_status {
+      for (int k = 0; k < chunk; ++k)
+        for (GroupStep& f : steps[k & 1]) IGAFD_TRY(f(gs));
+      const int nc = (int)cap_run.size();
+      hipLaunchKernelGGL(k_gather_flags, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, gs,
+                         arena.at<SolverState*>(flags_off), nc, dflags);
+      IGAFD_HIP_CHECK(hipGetLastError());
+      return IGAFD_OK;
+    };
+    while (true) {
+      run.clear();
+      for (int i = 0; i < count; ++i)
+        if (running[i]) run.push_back(i);
+      if (run.empty()) break;
+      const int nrun = (int)run.size();
+      const bool rebuild = captured_for < 0 || nrun < keep * captured_for;
+      if (rebuild) {
+        if (exec) IGAFD_BH(hipGraphExecDestroy(exec));
+        if (graph) IGAFD_BH(hipGraphDestroy(graph));
+        exec = nullptr;
+        graph = nullptr;
+        IGAFD_BT(sync_all());
+        IGAFD_BT(build_grouped(arena, steps, &flags_off, run, cs, xs, o->precision, o->flexible ? 1 : 0, Sp, z, zold));
+        IGAFD_BT(arena.upload(gs));
+        cap_run = run;
+        captured_for = nrun;
+      }
+      if (use_graph) {
+        if (rebuild) {
+          IGAFD_BH(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+          st = enqueue();
+          const hipError_t ec = hipStreamEndCapture(gs, &graph);
+          if (st != IGAFD_OK) {
+            cleanup();
+            return st;
+          }
+          IGAFD_BH(ec);
+          IGAFD_BH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        IGAFD_BH(hipGraphLaunch(exec, gs));
+      } else {
+        IGAFD_BT(enqueue());
+      }
+      IGAFD_BH(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * cap_run.size(), hipMemcpyDeviceToHost, gs));
+      IGAFD_BT(sync_all());
+      for (size_t k = 0; k < cap_run.size(); ++k)
+        running[cap_run[k]] = running[cap_run[k]] && hflags[k] == FLAG_RUNNING;
+    }
+  }
   // A graph captured for a set of running problems stays valid after some of
   // them converge (their kernels turn into no-ops on the device stop flag);
   // it is captured again only when the running count has fallen below
   // `keep` times the captured one, trading no-op launches against capture
   // and instantiation (a few ms for thousands of nodes).
-  double keep = 0.75;
-  if (const char* e = std::getenv("IGAFD_BATCH_RECAPTURE")) keep = std::atof(e);
-  while (true) {
+  while (!grouped) {
     int nrun = 0;
     for (int i = 0; i < count; ++i) nrun += running[i];
     if (nrun == 0) break;

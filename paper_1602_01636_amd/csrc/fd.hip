@@ -580,21 +580,20 @@ __device__ inline void two_step(typename Pr::acc (&acc)[kMaxTilesPerWave][NT], i
 // slice blockIdx.y and output columns k1 in [blockIdx.x * 16 NT, +16 NT).  X, Out:
 // slice-contiguous (n2 x n1); V1, V2 row-major, zero padded to npad1, npad2.
 template <class Pr, int NT, typename Tin, typename Tout, typename Tw, typename Tmid>
-__global__ __launch_bounds__(kFusedThreads) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
-                                                  const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
-                                                  int npad1, int npad2, Epi ep) {
+__device__ __forceinline__ void slice_body(const Tin* __restrict__ X, Tout* __restrict__ Out,
+                                           const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
+                                           int npad1, int npad2, const Epi& ep, int bx, int by, int gx) {
   using acc_t = typename Pr::acc;
   using V = typename Grp<Pr>::V;
   constexpr int kSliceCols = 16 * NT;
-  if (ep.flag && *ep.flag) return;
   extern __shared__ char smem_raw[];
   Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int mtiles = (n2 + 15) / 16;
   const int ldt = lds_ld<Tmid>(mtiles);
-  const int cb = blockIdx.x;
-  const long long sbase = (long long)blockIdx.y * n1 * n2;
+  const int cb = bx;
+  const long long sbase = (long long)by * n1 * n2;
   const Tin* Xs = X + sbase;
   acc_t acc[kMaxTilesPerWave][NT];
   // step 1: A = X (rows j2, contracted i1), B = V1^T (contracted i1, columns k1)
@@ -655,27 +654,58 @@ __global__ __launch_bounds__(kFusedThreads) void k_slice(const Tin* __restrict__
   }
   if (ep.flags & EPI_DOT) {
     const double sum = block_sum<kFusedThreads>(dot);
-    if (threadIdx.x == 0) ep.partial[blockIdx.x + (long long)gridDim.x * blockIdx.y] = sum;
+    if (threadIdx.x == 0) ep.partial[bx + (long long)gx * by] = sum;
   }
+}
+
+template <class Pr, int NT, typename Tin, typename Tout, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kFusedThreads) void k_slice(const Tin* __restrict__ X, Tout* __restrict__ Out,
+                                                  const Tw* __restrict__ V1, const Tw* __restrict__ V2, int n1, int n2,
+                                                  int npad1, int npad2, Epi ep) {
+  if (ep.flag && *ep.flag) return;
+  slice_body<Pr, NT, Tin, Tout, Tw, Tmid>(X, Out, V1, V2, n1, n2, npad1, npad2, ep, (int)blockIdx.x, (int)blockIdx.y,
+                                          (int)gridDim.x);
+}
+
+// Grouped form of a slice pass (several problems in one launch): job j owns
+// blocks [start[j], start[j+1]), gx column blocks per slice.
+template <typename Tin, typename Tout, typename Tw>
+struct SliceJob {
+  const Tin* X;
+  Tout* Out;
+  const Tw* V1;
+  const Tw* V2;
+  int n1, n2, npad1, npad2, gx;
+  Epi ep;
+};
+
+template <class Pr, int NT, typename Tin, typename Tout, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kFusedThreads) void k_slice_g(const SliceJob<Tin, Tout, Tw>* __restrict__ jobs,
+                                                    const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const SliceJob<Tin, Tout, Tw>& t = jobs[j];
+  if (t.ep.flag && *t.ep.flag) return;
+  const int local = (int)blockIdx.x - start[j];
+  slice_body<Pr, NT, Tin, Tout, Tw, Tmid>(t.X, t.Out, t.V1, t.V2, t.n1, t.n2, t.npad1, t.npad2, t.ep, local % t.gx,
+                                          local / t.gx, t.gx);
 }
 
 // Pass B: Out[i3][c] = sum_k3 Wb[i3][k3] (sum_j3 Wf[k3][j3] X[j3][c]) / lamsum(k3, c)
 // for the 32 columns c of block blockIdx.x (c = i2 n1 + i1, C = n1 n2).
 template <class Pr, typename Tw, typename Tmid>
-__global__ __launch_bounds__(kFusedThreads) void k_dir3(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
-                                                 const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
-                                                 int npad3, Epi ep) {
+__device__ __forceinline__ void dir3_body(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
+                                          const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
+                                          int npad3, const Epi& ep, int bx) {
   using acc_t = typename Pr::acc;
   using V = typename Grp<Pr>::V;
   constexpr int NT = kDir3Cols / 16;
-  if (ep.flag && *ep.flag) return;
   extern __shared__ char smem_raw[];
   Tmid* sT = reinterpret_cast<Tmid*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int mtiles = (n3 + 15) / 16;
   const int ldt = lds_ld<Tmid>(mtiles);
-  const int c0 = blockIdx.x * kDir3Cols;
+  const int c0 = bx * kDir3Cols;
   acc_t acc[kMaxTilesPerWave][NT];
   // the block's 32 input columns, staged transposed in LDS (column c holds its
   // n3 values contiguously, zeros up to the padded height) with 16-byte
@@ -732,6 +762,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_dir3(const Tmid* __restrict__
         if (i3 < n3 && c < C) Out[(long long)i3 * C + c] = (Tmid)acc[m][t][r];
       }
   }
+}
+
+template <class Pr, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kFusedThreads) void k_dir3(const Tmid* __restrict__ X, Tmid* __restrict__ Out,
+                                                 const Tw* __restrict__ Wf, const Tw* __restrict__ Wb, int n3, int C,
+                                                 int npad3, Epi ep) {
+  if (ep.flag && *ep.flag) return;
+  dir3_body<Pr, Tw, Tmid>(X, Out, Wf, Wb, n3, C, npad3, ep, (int)blockIdx.x);
+}
+
+template <typename Tw, typename Tmid>
+struct Dir3Job {
+  const Tmid* X;
+  Tmid* Out;
+  const Tw* Wf;
+  const Tw* Wb;
+  int n3, C, npad3;
+  Epi ep;
+};
+
+template <class Pr, typename Tw, typename Tmid>
+__global__ __launch_bounds__(kFusedThreads) void k_dir3_g(const Dir3Job<Tw, Tmid>* __restrict__ jobs,
+                                                   const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const Dir3Job<Tw, Tmid>& t = jobs[j];
+  if (t.ep.flag && *t.ep.flag) return;
+  dir3_body<Pr, Tw, Tmid>(t.X, t.Out, t.Wf, t.Wb, t.n3, t.C, t.npad3, t.ep, (int)blockIdx.x - start[j]);
 }
 
 // the fused path needs each direction's row tiles (at most 10) to fit the
@@ -1046,6 +1103,148 @@ igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const 
       set_error("unknown precision");
       return IGAFD_ERR_ARG;
   }
+}
+
+// ---- grouped FD applies (batched solves) ----
+
+namespace {
+
+template <class Pr, int NT, typename Tin, typename Tout, typename Tw, typename Tmid>
+igafd_status slice_g_launch(const GroupArena& a, size_t oj, size_t os, int nj, int blocks, size_t lds,
+                            hipStream_t st) {
+  hipLaunchKernelGGL((k_slice_g<Pr, NT, Tin, Tout, Tw, Tmid>), dim3((unsigned)blocks), dim3(kFusedThreads), lds, st,
+                     a.at<SliceJob<Tin, Tout, Tw>>(oj), a.at<int>(os), nj);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+// one slice pass for every problem: a launch per column-block width
+template <class Pr, typename Tin, typename Tout, typename Tw, typename Tmid>
+void slice_pass_g(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
+                  const std::vector<SliceJob<Tin, Tout, Tw>>& jobs) {
+  for (int nt : {3, 2}) {
+    std::vector<SliceJob<Tin, Tout, Tw>> jj;
+    std::vector<int> start(1, 0);
+    size_t lds = 0;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      const igafd_ctx* c = cs[i];
+      if (slice_nt(c->n[0]) != nt) continue;
+      jj.push_back(jobs[i]);
+      start.push_back(start.back() + jobs[i].gx * c->n[2]);
+      lds = std::max(lds, sizeof(Tmid) * (size_t)(16 * nt) * lds_ld<Tmid>((c->n[1] + 15) / 16));
+    }
+    if (jj.empty()) continue;
+    const size_t oj = a.push(jj.data(), sizeof(jj[0]) * jj.size());
+    const size_t os = a.push(start.data(), sizeof(int) * start.size());
+    const int nj = (int)jj.size(), blocks = start.back();
+    if (nt == 3)
+      steps.push_back([&a, oj, os, nj, blocks, lds](hipStream_t st) {
+        return slice_g_launch<Pr, 3, Tin, Tout, Tw, Tmid>(a, oj, os, nj, blocks, lds, st);
+      });
+    else
+      steps.push_back([&a, oj, os, nj, blocks, lds](hipStream_t st) {
+        return slice_g_launch<Pr, 2, Tin, Tout, Tw, Tmid>(a, oj, os, nj, blocks, lds, st);
+      });
+  }
+}
+
+template <class Pr, typename T, typename Tw>
+igafd_status fused_g(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
+                     const std::vector<const double*>& r, const std::vector<double*>& s,
+                     const std::vector<const double*>& S, const std::vector<double*>& partial) {
+  const int n = (int)cs.size();
+  std::vector<SliceJob<double, T, Tw>> ja(n);
+  std::vector<SliceJob<T, double, Tw>> jc(n);
+  std::vector<Dir3Job<Tw, T>> jb(n);
+  std::vector<int> start3(1, 0);
+  size_t lds3 = 0;
+  for (int i = 0; i < n; ++i) {
+    igafd_ctx* c = cs[i];
+    const DevDir* d = c->ddir;
+    const Tw* Wf[3];
+    const Tw* Wb[3];
+    for (int l = 0; l < 3; ++l) {
+      if constexpr (std::is_same<Tw, double>::value) {
+        Wf[l] = d[l].W64[0];
+        Wb[l] = d[l].W64[1];
+      } else {
+        Wf[l] = d[l].W32[0];
+        Wb[l] = d[l].W32[1];
+      }
+    }
+    const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+    T* b0 = reinterpret_cast<T*>(c->fdbuf[0]);
+    T* b1 = reinterpret_cast<T*>(c->fdbuf[1]);
+    const int* flag = &c->state->flag;
+    Epi e_in{}, e_lam{}, e_out{};
+    e_in.flag = e_lam.flag = e_out.flag = flag;
+    if (S[i]) {
+      e_in.flags |= EPI_PRESCALE;
+      e_in.S = S[i];
+      e_out.flags |= EPI_POSTSCALE;
+      e_out.S = S[i];
+    }
+    if (partial[i]) {
+      if (slice_blocks(c) > c->npartial) {
+        set_error("internal: FD grid larger than the partial-sum buffer");
+        return IGAFD_ERR_ARG;
+      }
+      e_out.flags |= EPI_DOT;
+      e_out.rdot = r[i];
+      e_out.partial = partial[i];
+    }
+    e_lam.n1 = n1;
+    e_lam.lamK = d[2].lam;
+    e_lam.lam1 = d[0].lam;
+    e_lam.lam2 = d[1].lam;
+    const int cols = 16 * slice_nt(n1), gx = (n1 + cols - 1) / cols, C = n1 * n2;
+    ja[i] = SliceJob<double, T, Tw>{r[i], b0, Wf[0], Wf[1], n1, n2, d[0].npad, d[1].npad, gx, e_in};
+    jb[i] = Dir3Job<Tw, T>{b0, b1, Wf[2], Wb[2], n3, C, d[2].npad, e_lam};
+    jc[i] = SliceJob<T, double, Tw>{b1, s[i], Wb[0], Wb[1], n1, n2, d[0].npad, d[1].npad, gx, e_out};
+    start3.push_back(start3.back() + (C + kDir3Cols - 1) / kDir3Cols);
+    lds3 = std::max(lds3, sizeof(T) * (size_t)kDir3Cols * lds_ld<T>((n3 + 15) / 16));
+  }
+  slice_pass_g<Pr, double, T, Tw, T>(a, steps, cs, ja);
+  const size_t ob = a.push(jb.data(), sizeof(jb[0]) * jb.size());
+  const size_t os = a.push(start3.data(), sizeof(int) * start3.size());
+  const int blocks3 = start3.back();
+  steps.push_back([&a, ob, os, n, blocks3, lds3](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL((k_dir3_g<Pr, Tw, T>), dim3((unsigned)blocks3), dim3(kFusedThreads), lds3, st,
+                       a.at<Dir3Job<Tw, T>>(ob), a.at<int>(os), n);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
+  slice_pass_g<Pr, T, double, Tw, T>(a, steps, cs, jc);
+  return IGAFD_OK;
+}
+
+}  // namespace
+
+igafd_status fd_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs, int prec,
+                        const std::vector<const double*>& r, const std::vector<double*>& s,
+                        const std::vector<const double*>& S, const std::vector<double*>& partial) {
+  for (const igafd_ctx* c : cs)
+    if (c->adi || c->hole >= 0 || !(c->fd_fused && fused_ok(c) && !use_gemm(c, prec))) {
+      set_error("internal: grouped FD apply needs the fused 3D passes");
+      return IGAFD_ERR_ARG;
+    }
+  switch (prec) {
+    case IGAFD_FP64:
+      return fused_g<PF64, double, double>(a, steps, cs, r, s, S, partial);
+    case IGAFD_FP32:
+      return fused_g<PF32, float, float>(a, steps, cs, r, s, S, partial);
+    case IGAFD_BF16:
+      return fused_g<PBF16, float, float>(a, steps, cs, r, s, S, partial);
+    case IGAFD_BF16X3:
+      return fused_g<PBF16X3, float, float>(a, steps, cs, r, s, S, partial);
+    default:
+      set_error("unknown precision");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+bool fd_groupable(const igafd_ctx* c, int prec) {
+  return !c->adi && c->hole < 0 && c->fd_fused && fused_ok(c) && !use_gemm(c, prec);
 }
 
 // Row padding of the U matrices: every row tile any tile count can address.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -202,4 +203,50 @@ void adi_free(igafd_ctx* c);
 // two independent 2D applies (no scaling, no partials) whose passes share launches
 igafd_status fd_apply_gemm2d_pair(int prec, igafd_ctx* c0, const double* r0, int ldr0, double* s0, int lds0,
                                   igafd_ctx* c1, const double* r1, int ldr1, double* s1, int lds1, const int* flag);
+
+// ---- grouped launches: one launch runs the same step for several problems ----
+// Block b of a grouped launch works on job j with start[j] <= b < start[j+1]
+// (start ascending, start[0] = 0).
+__device__ inline int group_job(const int* __restrict__ start, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Job tables of grouped launches: appended on the host, then copied to the
+// device once, before (and outside any capture of) the launches that read
+// them.  A step is one enqueued launch that reads its tables at `dev`.
+struct GroupArena {
+  std::vector<unsigned char> host;
+  unsigned char* dev = nullptr;
+  size_t cap = 0;
+  size_t push(const void* p, size_t bytes);  // offset (a multiple of 64) of the appended bytes
+  igafd_status upload(hipStream_t st);        // (re)allocates when too small; waits for the copy
+  void release();
+  template <class T>
+  const T* at(size_t off) const {
+    return reinterpret_cast<const T*>(dev + off);
+  }
+};
+using GroupStep = std::function<igafd_status(hipStream_t)>;
+
+// Per problem i of a grouped A product (3D problems): y_i = A_i x_i, x_i in the
+// zero-halo layout, block partials of (x_i, y_i) into partial_i, each problem
+// on the kernel and shape it has selected.
+igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
+                          const std::vector<const double*>& x, const std::vector<double*>& y,
+                          const std::vector<double*>& partial);
+bool spmv_groupable(const igafd_ctx* c);
+// Per problem i of a grouped FD apply (3D fused passes): s_i = M_i r_i with
+// M_i = P^-1 or S_i P^-1 S_i, block partials of (r_i, s_i) into partial_i.
+igafd_status fd_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs, int prec,
+                        const std::vector<const double*>& r, const std::vector<double*>& s,
+                        const std::vector<const double*>& S, const std::vector<double*>& partial);
+bool fd_groupable(const igafd_ctx* c, int prec);
 }  // namespace igafd

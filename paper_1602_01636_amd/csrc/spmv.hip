@@ -17,6 +17,7 @@
 // Optionally fuses the dot product (x, y) as one partial sum per block (fixed
 // reduction tree: deterministic).
 #include <algorithm>
+#include <map>
 
 #include "internal.h"
 #include "reduce.h"
@@ -51,16 +52,15 @@ __device__ __forceinline__ void pair_step(int o32, const double* __restrict__ ba
 }
 
 // band, x point at row 0 of plane 0 / of the vector (halos before and after).
+// Block bx of the rows.
 template <int D, int P, int R>
-__global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band, long long Ns,
-                                                 const double* __restrict__ x, double* __restrict__ y, int n1, int n2,
-                                                 long long N, double* __restrict__ partial,
-                                                 const int* __restrict__ flag, int hole) {
-  if (flag && *flag) return;  // CG already stopped: iteration enqueued ahead is a no-op
+__device__ __forceinline__ void row_body(const double* __restrict__ band, long long Ns, const double* __restrict__ x,
+                                         double* __restrict__ y, int n1, int n2, long long N,
+                                         double* __restrict__ partial, int hole, int bx) {
   constexpr int W = 2 * P + 1;
   constexpr int NPAIR = (D == 3) ? W * W : W;
   constexpr int MID = (NPAIR - 1) / 2;
-  const long long i0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * R;
+  const long long i0 = ((long long)bx * kBlock + threadIdx.x) * R;
   double dot = 0.0;
   if (i0 < N) {
     // rows of the removed quarter of an L-shaped domain (2D, hole >= 0) are
@@ -96,8 +96,38 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band
   }
   if (partial) {
     const double s = block_sum(dot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[bx] = s;
   }
+}
+
+template <int D, int P, int R>
+__global__ __launch_bounds__(kBlock) void k_spmv(const double* __restrict__ band, long long Ns,
+                                                 const double* __restrict__ x, double* __restrict__ y, int n1, int n2,
+                                                 long long N, double* __restrict__ partial,
+                                                 const int* __restrict__ flag, int hole) {
+  if (flag && *flag) return;  // CG already stopped: iteration enqueued ahead is a no-op
+  row_body<D, P, R>(band, Ns, x, y, n1, n2, N, partial, hole, (int)blockIdx.x);
+}
+
+// Grouped form (3D problems of one degree and row count per thread)
+struct RowJob {
+  const double* band;
+  long long Ns;
+  const double* x;
+  double* y;
+  int n1, n2;
+  long long N;
+  double* partial;
+  const int* flag;
+};
+
+template <int P, int R>
+__global__ __launch_bounds__(kBlock) void k_spmv_g(const RowJob* __restrict__ jobs, const int* __restrict__ start,
+                                                   int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const RowJob& t = jobs[j];
+  if (*t.flag) return;
+  row_body<3, P, R>(t.band, t.Ns, t.x, t.y, t.n1, t.n2, t.N, t.partial, -1, (int)blockIdx.x - start[j]);
 }
 
 // copy a vector into the interior of a zero-halo buffer; entries of the
@@ -261,15 +291,15 @@ __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restri
 // q = threadIdx.x + 256 m of the tile: rows 2q, 2q+1 of the concatenated runs.
 // The LDS tile allows about two blocks per CU: the occupancy target lets the
 // scheduler keep a chunk's loads in flight together.
+// tile_body: the work of tile `tile` (t2 fastest).
 template <int P, int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile(
-    const double* __restrict__ band, long long Ns, const double* __restrict__ x, double* __restrict__ ext, int n1,
-    int n2, int n3, int B2, int B3, int T2, const int* __restrict__ flag) {
-  if (flag && *flag) return;
+__device__ __forceinline__ void tile_body(const double* __restrict__ band, long long Ns, const double* __restrict__ x,
+                                          double* __restrict__ ext, int n1, int n2, int n3, int B2, int B3, int T2,
+                                          int tile) {
   extern __shared__ double lds[];
   const int E2 = B2 + 2 * P, E3 = B3 + P;
   const int elems = E2 * E3 * n1;
-  const int t2 = blockIdx.x % T2, t3 = blockIdx.x / T2;
+  const int t2 = tile % T2, t3 = tile / T2;
   const int a0 = t2 * B2, c0 = t3 * B3;
   for (int k = threadIdx.x; k < elems; k += kBlock) lds[k] = 0.0;
   const int run = B2 * n1;                                  // rows of one run (even)
@@ -324,21 +354,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   __syncthreads();
   // streaming stores: the tile buffer is read once, by k_spmv_combine (regular
   // stores made the kernel 4-6% slower at p = 3..5)
-  double* out = ext + (long long)blockIdx.x * elems;
+  double* out = ext + (long long)tile * elems;
   for (int k = threadIdx.x; k < elems; k += kBlock) __builtin_nontemporal_store(lds[k], out + k);
+}
+
+template <int P, int CH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile(
+    const double* __restrict__ band, long long Ns, const double* __restrict__ x, double* __restrict__ ext, int n1,
+    int n2, int n3, int B2, int B3, int T2, const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  tile_body<P, CH>(band, Ns, x, ext, n1, n2, n3, B2, B3, T2, (int)blockIdx.x);
+}
+
+// Grouped form: the tiles of several problems in one launch (block b works on
+// job j with start[j] <= b < start[j + 1]); a job whose CG has stopped exits.
+struct TileJob {
+  const double* band;
+  long long Ns;
+  const double* x;
+  double* ext;
+  int n1, n2, n3, B2, B3, T2;
+  const int* flag;
+};
+
+template <int P, int CH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile_g(
+    const TileJob* __restrict__ jobs, const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const TileJob& t = jobs[j];
+  if (*t.flag) return;
+  tile_body<P, CH>(t.band, t.Ns, t.x, t.ext, t.n1, t.n2, t.n3, t.B2, t.B3, t.T2, (int)blockIdx.x - start[j]);
 }
 
 __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
 // y[i] = sum over the tiles whose extended region holds row i (t3, then t2
-// ascending); optional per-block partial of (x, y).
-__global__ __launch_bounds__(kBlock) void k_spmv_combine(const double* __restrict__ ext,
-                                                         const double* __restrict__ x, double* __restrict__ y,
-                                                         int n1, int n2, int n3, int P, int B2, int B3, int T2,
-                                                         int T3, long long N, double* __restrict__ partial,
-                                                         const int* __restrict__ flag) {
-  if (flag && *flag) return;
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+// ascending); optional per-block partial of (x, y).  Block bx of the rows.
+__device__ __forceinline__ void combine_body(const double* __restrict__ ext, const double* __restrict__ x,
+                                             double* __restrict__ y, int n1, int n2, int n3, int P, int B2, int B3,
+                                             int T2, int T3, long long N, double* __restrict__ partial, int bx) {
+  const long long i = (long long)bx * kBlock + threadIdx.x;
   double dot = 0.0;
   if (i < N) {
     const int i1 = (int)(i % n1);
@@ -359,8 +414,36 @@ __global__ __launch_bounds__(kBlock) void k_spmv_combine(const double* __restric
   }
   if (partial) {
     const double sum = block_sum(dot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+    if (threadIdx.x == 0) partial[bx] = sum;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv_combine(const double* __restrict__ ext,
+                                                         const double* __restrict__ x, double* __restrict__ y,
+                                                         int n1, int n2, int n3, int P, int B2, int B3, int T2,
+                                                         int T3, long long N, double* __restrict__ partial,
+                                                         const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  combine_body(ext, x, y, n1, n2, n3, P, B2, B3, T2, T3, N, partial, (int)blockIdx.x);
+}
+
+struct CombineJob {
+  const double* ext;
+  const double* x;
+  double* y;
+  int n1, n2, n3, P, B2, B3, T2, T3;
+  long long N;
+  double* partial;
+  const int* flag;
+};
+
+__global__ __launch_bounds__(kBlock) void k_spmv_combine_g(const CombineJob* __restrict__ jobs,
+                                                           const int* __restrict__ start, int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const CombineJob& t = jobs[j];
+  if (*t.flag) return;
+  combine_body(t.ext, t.x, t.y, t.n1, t.n2, t.n3, t.P, t.B2, t.B3, t.T2, t.T3, t.N, t.partial,
+               (int)blockIdx.x - start[j]);
 }
 
 template <int D, int P, int R>
@@ -599,6 +682,194 @@ igafd_status mask_hole(igafd_ctx* c, double* y) {
   hipLaunchKernelGGL(k_zero_hole, dim3((unsigned)((w * w + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, y,
                      c->n[0], c->hole);
   IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+// ---- grouped A products (batched solves) ----
+
+bool spmv_groupable(const igafd_ctx* c) { return c->dim == 3 && c->p >= 1 && c->p <= kMaxDegree; }
+
+namespace {
+
+template <int P, int CH>
+igafd_status tile_g_launch(const TileJob* jobs, const int* start, int njobs, int blocks, size_t lds,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv_tile_g<P, CH>), dim3((unsigned)blocks), dim3(kBlock), lds, st, jobs, start, njobs);
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+template <int P, int CH>
+igafd_status tile_g_attr(size_t lds) {
+  IGAFD_HIP_CHECK(hipFuncSetAttribute((const void*)k_spmv_tile_g<P, CH>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return IGAFD_OK;
+}
+
+// (p, chunk count) -> the grouped tile kernel's launch or attribute call
+template <int P>
+igafd_status tile_g_dispatch(int ch, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks,
+                             size_t lds, hipStream_t st) {
+  switch (ch) {
+#define IGAFD_CH(K) \
+  case K:           \
+    return attr ? tile_g_attr<P, K>(lds) : tile_g_launch<P, K>(jobs, start, njobs, blocks, lds, st);
+    IGAFD_CH(1) IGAFD_CH(2) IGAFD_CH(3) IGAFD_CH(4) IGAFD_CH(5) IGAFD_CH(6) IGAFD_CH(7) IGAFD_CH(8)
+#undef IGAFD_CH
+    default:
+      set_error("internal: bad tile chunk count");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+template <int P>
+igafd_status row_g_dispatch(int r, const RowJob* jobs, const int* start, int njobs, int blocks, hipStream_t st) {
+  switch (r) {
+    case 1:
+      hipLaunchKernelGGL((k_spmv_g<P, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, st, jobs, start, njobs);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_spmv_g<P, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, jobs, start, njobs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv_g<P, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, jobs, start, njobs);
+      break;
+  }
+  IGAFD_HIP_CHECK(hipGetLastError());
+  return IGAFD_OK;
+}
+
+igafd_status row_g(int p, int r, const RowJob* jobs, const int* start, int njobs, int blocks, hipStream_t st) {
+  switch (p) {
+#define IGAFD_TCASE(P) \
+  case P:              \
+    return row_g_dispatch<P>(r, jobs, start, njobs, blocks, st);
+    IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
+#undef IGAFD_TCASE
+    default:
+      set_error("unsupported degree");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+igafd_status tile_g(int p, int ch, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks, size_t lds,
+                    hipStream_t st) {
+  switch (p) {
+#define IGAFD_TCASE(P) \
+  case P:              \
+    return tile_g_dispatch<P>(ch, attr, jobs, start, njobs, blocks, lds, st);
+    IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
+#undef IGAFD_TCASE
+    default:
+      set_error("unsupported degree");
+      return IGAFD_ERR_ARG;
+  }
+}
+
+}  // namespace
+
+igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
+                          const std::vector<const double*>& x, const std::vector<double*>& y,
+                          const std::vector<double*>& partial) {
+  const int n = (int)cs.size();
+  if (n == 0) return IGAFD_OK;
+  // tiled problems: a launch per (degree, chunk count), the dynamic LDS the
+  // largest accumulator of the group, then one combine launch; row-parallel
+  // problems: a launch per (degree, rows per thread)
+  std::map<std::pair<int, int>, std::vector<int>> tgroups, rgroups;
+  std::vector<int> tiled;
+  for (int i = 0; i < n; ++i) {
+    const igafd_ctx* c = cs[i];
+    if (!spmv_groupable(c)) {
+      set_error("internal: grouped A product needs 3D problems");
+      return IGAFD_ERR_ARG;
+    }
+    const int p = c->p;
+    if (c->tile_b2 > 0) {
+      const int ch = tile_chunks(c->tile_b2, c->tile_b3, c->n[0]);
+      const long long T2 = (c->n[1] + c->tile_b2 - 1) / c->tile_b2, T3 = (c->n[2] + c->tile_b3 - 1) / c->tile_b3;
+      if (T2 * T3 * (c->tile_b2 + 2 * p) * (c->tile_b3 + p) * (long long)c->n[0] > c->ext_cap || ch < 1 ||
+          ch > kTileMaxCh) {
+        set_error("internal: tile shape does not fit the tile buffer");
+        return IGAFD_ERR_ARG;
+      }
+      if (partial[i] && (c->N + kBlock - 1) / kBlock > c->npartial) {
+        set_error("internal: A-product grid larger than the partial-sum buffer");
+        return IGAFD_ERR_ARG;
+      }
+      tgroups[{p, ch}].push_back(i);
+      tiled.push_back(i);
+    } else {
+      const int R = (c->spmv_rows == 1 || c->spmv_rows == 4) ? c->spmv_rows : 2;
+      if (partial[i] && spmv_blocks(c) > c->npartial) {
+        set_error("internal: A-product grid larger than the partial-sum buffer");
+        return IGAFD_ERR_ARG;
+      }
+      rgroups[{p, R}].push_back(i);
+    }
+  }
+  for (const auto& g : rgroups) {
+    const int p = g.first.first, R = g.first.second;
+    std::vector<RowJob> jobs;
+    std::vector<int> start(1, 0);
+    for (int i : g.second) {
+      igafd_ctx* c = cs[i];
+      jobs.push_back(RowJob{c->band + c->halo, c->Ns, x[i], y[i], c->n[0], c->n[1], c->N, partial[i],
+                            &c->state->flag});
+      start.push_back(start.back() + spmv_blocks(c));
+    }
+    const size_t oj = a.push(jobs.data(), sizeof(RowJob) * jobs.size());
+    const size_t os = a.push(start.data(), sizeof(int) * start.size());
+    const int nj = (int)jobs.size(), blocks = start.back();
+    steps.push_back([&a, p, R, oj, os, nj, blocks](hipStream_t st) {
+      return row_g(p, R, a.at<RowJob>(oj), a.at<int>(os), nj, blocks, st);
+    });
+  }
+  for (const auto& g : tgroups) {
+    const int p = g.first.first, ch = g.first.second;
+    std::vector<TileJob> jobs;
+    std::vector<int> start(1, 0);
+    size_t lds = 0;
+    for (int i : g.second) {
+      igafd_ctx* c = cs[i];
+      const int B2 = c->tile_b2, B3 = c->tile_b3;
+      const int T2 = (c->n[1] + B2 - 1) / B2, T3 = (c->n[2] + B3 - 1) / B3;
+      jobs.push_back(TileJob{c->band + c->halo, c->Ns, x[i], c->ext, c->n[0], c->n[1], c->n[2], B2, B3, T2,
+                             &c->state->flag});
+      start.push_back(start.back() + T2 * T3);
+      lds = std::max(lds, sizeof(double) * ((size_t)(B2 + 2 * p) * (B3 + p) * c->n[0] + 2 * 64));
+    }
+    if (lds > 65536) {
+      const igafd_status sa = tile_g(p, ch, true, nullptr, nullptr, 0, 0, lds, nullptr);
+      if (sa != IGAFD_OK) return sa;
+    }
+    const size_t oj = a.push(jobs.data(), sizeof(TileJob) * jobs.size());
+    const size_t os = a.push(start.data(), sizeof(int) * start.size());
+    const int nj = (int)jobs.size(), blocks = start.back();
+    steps.push_back([&a, p, ch, oj, os, nj, blocks, lds](hipStream_t st) {
+      return tile_g(p, ch, false, a.at<TileJob>(oj), a.at<int>(os), nj, blocks, lds, st);
+    });
+  }
+  if (tiled.empty()) return IGAFD_OK;
+  std::vector<CombineJob> cj;
+  std::vector<int> start(1, 0);
+  for (int i : tiled) {
+    igafd_ctx* c = cs[i];
+    const int B2 = c->tile_b2, B3 = c->tile_b3;
+    const int T2 = (c->n[1] + B2 - 1) / B2, T3 = (c->n[2] + B3 - 1) / B3;
+    cj.push_back(CombineJob{c->ext, x[i], y[i], c->n[0], c->n[1], c->n[2], c->p, B2, B3, T2, T3, c->N, partial[i],
+                            &c->state->flag});
+    start.push_back(start.back() + (int)((c->N + kBlock - 1) / kBlock));
+  }
+  const size_t oj = a.push(cj.data(), sizeof(CombineJob) * cj.size());
+  const size_t os = a.push(start.data(), sizeof(int) * start.size());
+  const int nc = (int)cj.size(), blocks = start.back();
+  steps.push_back([&a, oj, os, nc, blocks](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL(k_spmv_combine_g, dim3((unsigned)blocks), dim3(kBlock), 0, st, a.at<CombineJob>(oj),
+                       a.at<int>(os), nc);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
   return IGAFD_OK;
 }
 
