@@ -1,6 +1,6 @@
-"""GPU: batched solves of uneven problems (graph-captured chunks over a stream
-pool) give the same iterates as one-at-a-time solves (same kernels, same
-reduction order: bitwise), and match the oracle."""
+"""GPU: batched solves of uneven problems (grouped launches or a stream pool,
+graph-captured chunks) give the same iterates as one-at-a-time solves (same
+kernel bodies, same reduction order: bitwise), and match the oracle."""
 import numpy as np
 import pytest
 
@@ -29,11 +29,15 @@ def _batch_problems():
     return out
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batched_equals_individual(api, graph, monkeypatch):
+@pytest.mark.parametrize("graph,grouped", [(True, True), (False, True), (True, False)])
+def test_batched_equals_individual(api, graph, grouped, monkeypatch):
+    """Grouped launches (every step one launch over all problems) and the
+    stream pool, with and without graph capture: bitwise the single solves."""
     import torch
     if not graph:
         monkeypatch.setenv("IGAFD_NO_GRAPH", "1")
+    if not grouped:
+        monkeypatch.setenv("IGAFD_BATCH_GROUPED", "0")
     probs = _batch_problems()
     ctxs = [api.igafd_setup(pr) for pr in probs]
     bs, us, ref = [], [], []
@@ -96,3 +100,30 @@ def test_batched_matches_oracle_and_autotune(api):
         assert abs(infos[0]["iters"] - info_or["iters"]) <= 1
         assert rel(to_host(u1), u_or) <= 1e-7
         assert infos[1]["true_relres"] <= 1e-8
+
+
+def test_batched_scaled_equals_individual(api):
+    """S P^-1 S in the grouped batch (the scaling in the first and last FD
+    passes of each problem's jobs): bitwise the single scaled solves."""
+    import torch
+    probs = _batch_problems()[:4]
+    ctxs = [api.igafd_setup(pr) for pr in probs]
+    try:
+        bs, us, ref = [], [], []
+        for c in ctxs:
+            api.igafd_set_scaling_diag_ratio(c)
+            b = torch.zeros(c.N, dtype=torch.float64, device="cuda")
+            api.igafd_load_vector(c, synth.RHS_SINPROD, b)
+            u = torch.zeros_like(b)
+            info = api.igafd_solve(c, b, u, use_scaling=True)
+            ref.append((info, u.clone()))
+            bs.append(b)
+            us.append(torch.zeros_like(b))
+        infos, _ = api.igafd_solve_batched(ctxs, bs, us, use_scaling=True)
+        for (info_ref, u_ref), info, u in zip(ref, infos, us):
+            assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+            assert info["iters"] == info_ref["iters"]
+            assert torch.equal(u, u_ref)
+    finally:
+        for c in ctxs:
+            c.close()
