@@ -67,6 +67,60 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ b, c
   }
 }
 
+// Grouped start of batched solves: r = b, x = 0, partials (b, b), (r, r);
+// and r = b - q with the partials (r, r) of the true residual.
+struct InitJob {
+  const double* b;
+  const double* q;  // null: r = b, x = 0 (start); else r = b - q (true residual)
+  double* r;
+  double* x;
+  long long N;
+  double* partial;
+  int gx;
+};
+
+__global__ __launch_bounds__(kBlock) void k_init_g(const InitJob* __restrict__ jobs, const int* __restrict__ start,
+                                                   int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const InitJob& t = jobs[j];
+  const int bx = (int)blockIdx.x - start[j];
+  const long long i = (long long)bx * kBlock + threadIdx.x;
+  double bb = 0.0, rr = 0.0;
+  if (i < t.N) {
+    const double bi = t.b[i];
+    const double ri = t.q ? bi - t.q[i] : bi;
+    t.r[i] = ri;
+    if (!t.q) t.x[i] = 0.0;
+    bb = bi * bi;
+    rr = ri * ri;
+  }
+  if (t.q) {
+    const double s = block_sum(rr);
+    if (threadIdx.x == 0) t.partial[bx] = s;
+  } else {
+    block_sum2(bb, rr);
+    if (threadIdx.x == 0) {
+      t.partial[bx] = bb;
+      t.partial[t.gx + bx] = rr;
+    }
+  }
+}
+
+// dst = src over N values per job (into the zero-halo buffers)
+struct CopyJob {
+  const double* src;
+  double* dst;
+  long long N;
+};
+
+__global__ __launch_bounds__(kBlock) void k_copy_g(const CopyJob* __restrict__ jobs, const int* __restrict__ start,
+                                                   int njobs) {
+  const int j = group_job(start, njobs, (int)blockIdx.x);
+  const CopyJob& t = jobs[j];
+  const long long i = (long long)((int)blockIdx.x - start[j]) * kBlock + threadIdx.x;
+  if (i < t.N) t.dst[i] = t.src[i];
+}
+
 // One block: sum partial[0..count) (and partial[count..2 count) when two
 // sums are pending) in a fixed order, then the scalar step of CG.
 constexpr int kReduceBlock = 1024;  // one wide block: a few independent loads per thread
@@ -215,14 +269,14 @@ struct UpdatePJob {
   long long N;
 };
 
+template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_update_p_g(const UpdatePJob* __restrict__ jobs,
                                                        const int* __restrict__ start, int njobs) {
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const UpdatePJob& t = jobs[j];
-  if (t.s->flag != FLAG_RUNNING) return;
-  const double beta = t.s->beta;
+  if (!FIRST && t.s->flag != FLAG_RUNNING) return;
   const long long i = (long long)((int)blockIdx.x - start[j]) * kBlock + threadIdx.x;
-  if (i < t.N) t.p[i] = fma(beta, t.p[i], t.z[i]);
+  if (i < t.N) t.p[i] = FIRST ? t.z[i] : fma(t.s->beta, t.p[i], t.z[i]);
 }
 
 // flags[j] = the CG flag of problem j (one copy to the host per check)
@@ -775,6 +829,7 @@ size_t GroupArena::push(const void* p, size_t bytes) {
 igafd_status GroupArena::upload(hipStream_t st) {
   if (host.empty()) return IGAFD_OK;
   if (!dev || cap < host.size()) {
+    IGAFD_HIP_CHECK(hipStreamSynchronize(st));  // launches reading the old tables are done
     if (dev) IGAFD_HIP_CHECK(hipFree(dev));
     dev = nullptr;
     cap = 0;
@@ -896,13 +951,140 @@ igafd_status build_grouped(GroupArena& a, std::vector<GroupStep> (&steps)[2], si
       const size_t os = a.push(start.data(), sizeof(int) * start.size());
       const int blocks = start.back();
       st.push_back([&a, oj, os, n, blocks](hipStream_t s0) -> igafd_status {
-        hipLaunchKernelGGL(k_update_p_g, dim3((unsigned)blocks), dim3(kBlock), 0, s0, a.at<UpdatePJob>(oj),
+        hipLaunchKernelGGL(k_update_p_g<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s0, a.at<UpdatePJob>(oj),
                            a.at<int>(os), n);
         IGAFD_HIP_CHECK(hipGetLastError());
         return IGAFD_OK;
       });
     }
   }
+  return IGAFD_OK;
+}
+
+// Grouped phases of a batched solve outside the iteration loop, for the
+// problems `ids` (each one launch per step, tables in `a`):
+// init: r = b, x = 0, then ||b||^2, ||r||^2 and the stop test (RED_BB_RR);
+// *flags_off: the table of state pointers for k_gather_flags.
+igafd_status build_grouped_init(GroupArena& a, std::vector<GroupStep>& steps, size_t* flags_off,
+                                const std::vector<int>& ids, igafd_ctx* const* cs, const double* const* bs,
+                                double* const* xs) {
+  a.host.clear();
+  steps.clear();
+  const int n = (int)ids.size();
+  std::vector<InitJob> jobs;
+  std::vector<ReduceJob> red;
+  std::vector<SolverState*> states;
+  std::vector<int> start(1, 0);
+  for (int i : ids) {
+    igafd_ctx* c = cs[i];
+    const int vb = (int)vblocks(c);
+    IGAFD_TRY(check_partials(c, vb));  // two sums of vb partials: the buffer holds 2 npartial
+    jobs.push_back(InitJob{bs[i], nullptr, c->r, xs[i], c->N, c->partial, vb});
+    red.push_back(ReduceJob{c->partial, vb, 1, c->state});
+    states.push_back(c->state);
+    start.push_back(start.back() + vb);
+  }
+  *flags_off = a.push(states.data(), sizeof(SolverState*) * states.size());
+  const size_t oj = a.push(jobs.data(), sizeof(InitJob) * jobs.size());
+  const size_t os = a.push(start.data(), sizeof(int) * start.size());
+  const size_t orr = a.push(red.data(), sizeof(ReduceJob) * red.size());
+  const int blocks = start.back();
+  steps.push_back([&a, oj, os, orr, n, blocks](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL(k_init_g, dim3((unsigned)blocks), dim3(kBlock), 0, st, a.at<InitJob>(oj), a.at<int>(os), n);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)n), dim3(kReduceBlock), 0, st, a.at<ReduceJob>(orr), (int)RED_BB_RR);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
+  return IGAFD_OK;
+}
+
+// first directions of the running problems: z = M r, rho = (r, z), p = z
+igafd_status build_grouped_start(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<int>& run,
+                                 igafd_ctx* const* cs, int prec, const std::vector<const double*>& Sp,
+                                 const std::vector<double*>& z) {
+  a.host.clear();
+  steps.clear();
+  const int n = (int)run.size();
+  std::vector<igafd_ctx*> cc;
+  std::vector<const double*> rv, S;
+  std::vector<double*> zz, part;
+  std::vector<ReduceJob> red;
+  std::vector<UpdatePJob> pj;
+  std::vector<int> start(1, 0);
+  for (int i : run) {
+    igafd_ctx* c = cs[i];
+    const int cnt = fd_dot_blocks(c, prec);
+    IGAFD_TRY(check_partials(c, cnt));
+    cc.push_back(c);
+    rv.push_back(c->r);
+    S.push_back(Sp[i]);
+    zz.push_back(z[i]);
+    part.push_back(c->partial);
+    red.push_back(ReduceJob{c->partial, cnt, 0, c->state});
+    pj.push_back(UpdatePJob{c->pv, z[i], c->state, c->N});
+    start.push_back(start.back() + (int)vblocks(c));
+  }
+  IGAFD_TRY(fd_grouped(a, steps, cc, prec, rv, zz, S, part));
+  const size_t orr = a.push(red.data(), sizeof(ReduceJob) * red.size());
+  const size_t oj = a.push(pj.data(), sizeof(UpdatePJob) * pj.size());
+  const size_t os = a.push(start.data(), sizeof(int) * start.size());
+  const int blocks = start.back();
+  steps.push_back([&a, orr, oj, os, n, blocks](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)n), dim3(kReduceBlock), 0, st, a.at<ReduceJob>(orr), (int)RED_RHO0);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_update_p_g<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, a.at<UpdatePJob>(oj),
+                       a.at<int>(os), n);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
+  return IGAFD_OK;
+}
+
+// FP64 true residuals: x into the zero-halo buffer, q = A x (every problem,
+// stopped or not), r = b - q, ||r||^2 (RED_TRUE)
+igafd_status build_grouped_residual(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<int>& ids,
+                                    igafd_ctx* const* cs, const double* const* bs, double* const* xs) {
+  a.host.clear();
+  steps.clear();
+  const int n = (int)ids.size();
+  std::vector<igafd_ctx*> cc;
+  std::vector<const double*> xp;
+  std::vector<double*> q, nopart(n, nullptr);
+  std::vector<CopyJob> cj;
+  std::vector<InitJob> rj;
+  std::vector<ReduceJob> red;
+  std::vector<int> start(1, 0);
+  for (int i : ids) {
+    igafd_ctx* c = cs[i];
+    const int vb = (int)vblocks(c);
+    IGAFD_TRY(check_partials(c, vb));
+    cc.push_back(c);
+    xp.push_back(c->xpad + c->halo);
+    q.push_back(c->q);
+    cj.push_back(CopyJob{xs[i], c->xpad + c->halo, c->N});
+    rj.push_back(InitJob{bs[i], c->q, c->r, nullptr, c->N, c->partial, vb});
+    red.push_back(ReduceJob{c->partial, vb, 0, c->state});
+    start.push_back(start.back() + vb);
+  }
+  const size_t oc = a.push(cj.data(), sizeof(CopyJob) * cj.size());
+  const size_t os = a.push(start.data(), sizeof(int) * start.size());
+  const int blocks = start.back();
+  steps.push_back([&a, oc, os, n, blocks](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL(k_copy_g, dim3((unsigned)blocks), dim3(kBlock), 0, st, a.at<CopyJob>(oc), a.at<int>(os), n);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
+  IGAFD_TRY(spmv_grouped(a, steps, cc, xp, q, nopart, false));
+  const size_t orj = a.push(rj.data(), sizeof(InitJob) * rj.size());
+  const size_t orr = a.push(red.data(), sizeof(ReduceJob) * red.size());
+  steps.push_back([&a, orj, orr, os, n, blocks](hipStream_t st) -> igafd_status {
+    hipLaunchKernelGGL(k_init_g, dim3((unsigned)blocks), dim3(kBlock), 0, st, a.at<InitJob>(orj), a.at<int>(os), n);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)n), dim3(kReduceBlock), 0, st, a.at<ReduceJob>(orr), (int)RED_TRUE);
+    IGAFD_HIP_CHECK(hipGetLastError());
+    return IGAFD_OK;
+  });
   return IGAFD_OK;
 }
 
@@ -949,9 +1131,9 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
     }
     Sp[i] = use ? cs[i]->scaling : nullptr;
   }
-  // every problem on the tiled A product and the fused FD passes: one stream,
-  // each step of an iteration one grouped launch over all running problems;
-  // otherwise a pool of streams, one problem's launches after another's
+  // every problem 3D with the fused FD passes: each step of an iteration one
+  // grouped launch over all running problems; otherwise a pool of streams,
+  // one problem's launches after another's
   const bool grouped = batch_groupable(cs, count, o->precision);
   int nst = 8;
   if (const char* e = std::getenv("IGAFD_BATCH_STREAMS")) nst = std::max(1, std::min(32, std::atoi(e)));
@@ -985,7 +1167,8 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (pool[0]) (void)hipStreamSynchronize(pool[0]);
+    for (hipStream_t q : pool)
+      if (q) (void)hipStreamSynchronize(q);
     arena.release();
     if (dflags) (void)hipFree(dflags);
     // the callers' streams continue after everything the pool ran
@@ -1045,28 +1228,66 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   IGAFD_BH(hipEventRecord(t0, pool[0]));
   for (int k = 1; k < nst; ++k) IGAFD_BH(hipStreamWaitEvent(pool[k], t0, 0));
   // init: r = b, x = 0, ||b||, ||r||; then the first directions
-  for (int i = 0; i < count; ++i) {
-    igafd_ctx* c = cs[i];
-    SolverState init{};
-    init.tol2 = o->rtol * o->rtol;
-    init.maxit = maxit;
-    init.flexible = o->flexible ? 1 : 0;
-    *c->hstate = init;
-    IGAFD_BH(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
-    const unsigned vb = vblocks(c);
-    hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], nullptr, c->r, xs[i], 0, c->N, c->partial);
+  std::vector<int> hflags(count, 0);
+  if (grouped) {
+    IGAFD_BH(hipMalloc((void**)&dflags, sizeof(int) * count));
+    std::vector<int> all(count);
+    for (int i = 0; i < count; ++i) all[i] = i;
+    std::vector<GroupStep> ph;
+    size_t foff = 0;
+    for (int i = 0; i < count; ++i) {
+      igafd_ctx* c = cs[i];
+      SolverState init{};
+      init.tol2 = o->rtol * o->rtol;
+      init.maxit = maxit;
+      init.flexible = o->flexible ? 1 : 0;
+      *c->hstate = init;
+      IGAFD_BH(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, pool[0]));
+    }
+    IGAFD_BT(build_grouped_init(arena, ph, &foff, all, cs, bs, xs));
+    IGAFD_BT(arena.upload(pool[0]));
+    for (GroupStep& f : ph) IGAFD_BT(f(pool[0]));
+    hipLaunchKernelGGL(k_gather_flags, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, pool[0],
+                       arena.at<SolverState*>(foff), count, dflags);
     IGAFD_BH(hipGetLastError());
-    IGAFD_BT(reduce(c, (int)vb, 1, RED_BB_RR, nullptr));
-    IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
-  }
-  IGAFD_BT(sync_all());
-  for (int i = 0; i < count; ++i) {
-    igafd_ctx* c = cs[i];
-    z[i] = c->z;
-    zold[i] = c->zold;
-    running[i] = c->hstate->flag == FLAG_RUNNING;
-    if (running[i])
-      IGAFD_BT(start_directions(c, o->precision, Sp[i], z[i], zold[i]));
+    IGAFD_BH(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * count, hipMemcpyDeviceToHost, pool[0]));
+    IGAFD_BT(sync_all());
+    std::vector<int> run;
+    for (int i = 0; i < count; ++i) {
+      z[i] = cs[i]->z;
+      zold[i] = cs[i]->zold;
+      running[i] = hflags[i] == FLAG_RUNNING;
+      if (running[i]) run.push_back(i);
+    }
+    if (!run.empty()) {
+      IGAFD_BT(build_grouped_start(arena, ph, run, cs, o->precision, Sp, z));
+      IGAFD_BT(arena.upload(pool[0]));
+      for (GroupStep& f : ph) IGAFD_BT(f(pool[0]));
+    }
+  } else {
+    for (int i = 0; i < count; ++i) {
+      igafd_ctx* c = cs[i];
+      SolverState init{};
+      init.tol2 = o->rtol * o->rtol;
+      init.maxit = maxit;
+      init.flexible = o->flexible ? 1 : 0;
+      *c->hstate = init;
+      IGAFD_BH(hipMemcpyAsync(c->state, c->hstate, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
+      const unsigned vb = vblocks(c);
+      hipLaunchKernelGGL(k_init, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], nullptr, c->r, xs[i], 0, c->N,
+                         c->partial);
+      IGAFD_BH(hipGetLastError());
+      IGAFD_BT(reduce(c, (int)vb, 1, RED_BB_RR, nullptr));
+      IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+    }
+    IGAFD_BT(sync_all());
+    for (int i = 0; i < count; ++i) {
+      igafd_ctx* c = cs[i];
+      z[i] = c->z;
+      zold[i] = c->zold;
+      running[i] = c->hstate->flag == FLAG_RUNNING;
+      if (running[i]) IGAFD_BT(start_directions(c, o->precision, Sp[i], z[i], zold[i]));
+    }
   }
   const bool use_graph = std::getenv("IGAFD_NO_GRAPH") == nullptr;
   int captured_for = -1;
@@ -1078,9 +1299,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
     // falls below `keep` times the captured one
     std::vector<GroupStep> steps[2];
     std::vector<int> run, cap_run;
-    std::vector<int> hflags(count, 0);
     size_t flags_off = 0;
-    IGAFD_BH(hipMalloc((void**)&dflags, sizeof(int) * count));
     const hipStream_t gs = pool[0];
     auto enqueue = [&]() -> igafd_status {
       for (int k = 0; k < chunk; ++k)
@@ -1103,7 +1322,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
         if (graph) IGAFD_BH(hipGraphDestroy(graph));
         exec = nullptr;
         graph = nullptr;
-        IGAFD_BT(sync_all());
+        IGAFD_BH(hipStreamSynchronize(gs));
         IGAFD_BT(build_grouped(arena, steps, &flags_off, run, cs, xs, o->precision, o->flexible ? 1 : 0, Sp, z, zold));
         IGAFD_BT(arena.upload(gs));
         cap_run = run;
@@ -1126,7 +1345,7 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
         IGAFD_BT(enqueue());
       }
       IGAFD_BH(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * cap_run.size(), hipMemcpyDeviceToHost, gs));
-      IGAFD_BT(sync_all());
+      IGAFD_BH(hipStreamSynchronize(gs));
       for (size_t k = 0; k < cap_run.size(); ++k)
         running[cap_run[k]] = running[cap_run[k]] && hflags[k] == FLAG_RUNNING;
     }
@@ -1191,14 +1410,25 @@ igafd_status solve_batched_impl(igafd_ctx* const* cs, int count, const double* c
   IGAFD_BH(hipEventElapsedTime(&ms, t0, t1));
   if (wall_ms) *wall_ms = ms;
   // FP64 true residuals; a problem that misses the tolerance continues alone
-  for (int i = 0; i < count; ++i) {
-    igafd_ctx* c = cs[i];
-    const unsigned vb = vblocks(c);
-    IGAFD_BT(spmv_unpadded(c, xs[i], c->q, nullptr, nullptr));
-    hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], c->q, c->r, c->N, c->partial);
-    IGAFD_BH(hipGetLastError());
-    IGAFD_BT(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
-    IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+  if (grouped) {
+    std::vector<int> all(count);
+    for (int i = 0; i < count; ++i) all[i] = i;
+    std::vector<GroupStep> ph;
+    IGAFD_BT(build_grouped_residual(arena, ph, all, cs, bs, xs));
+    IGAFD_BT(arena.upload(pool[0]));
+    for (GroupStep& f : ph) IGAFD_BT(f(pool[0]));
+    for (int i = 0; i < count; ++i)
+      IGAFD_BH(hipMemcpyAsync(cs[i]->hstate, cs[i]->state, sizeof(SolverState), hipMemcpyDeviceToHost, pool[0]));
+  } else {
+    for (int i = 0; i < count; ++i) {
+      igafd_ctx* c = cs[i];
+      const unsigned vb = vblocks(c);
+      IGAFD_BT(spmv_unpadded(c, xs[i], c->q, nullptr, nullptr));
+      hipLaunchKernelGGL(k_residual, dim3(vb), dim3(kBlock), 0, c->stream, bs[i], c->q, c->r, c->N, c->partial);
+      IGAFD_BH(hipGetLastError());
+      IGAFD_BT(reduce(c, (int)vb, 0, RED_TRUE, nullptr));
+      IGAFD_BH(hipMemcpyAsync(c->hstate, c->state, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+    }
   }
   IGAFD_BT(sync_all());
   for (int i = 0; i < count; ++i) {

@@ -237,11 +237,12 @@ struct GroupArena {
 using GroupStep = std::function<igafd_status(hipStream_t)>;
 
 // Per problem i of a grouped A product (3D problems): y_i = A_i x_i, x_i in the
-// zero-halo layout, block partials of (x_i, y_i) into partial_i, each problem
-// on the kernel and shape it has selected.
+// zero-halo layout, block partials of (x_i, y_i) into partial_i (may be null),
+// each problem on the kernel and shape it has selected; stop_flags: a problem
+// whose CG has stopped is skipped (its stop flag is set).
 igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
                           const std::vector<const double*>& x, const std::vector<double*>& y,
-                          const std::vector<double*>& partial);
+                          const std::vector<double*>& partial, bool stop_flags = true);
 bool spmv_groupable(const igafd_ctx* c);
 // Per problem i of a grouped FD apply (3D fused passes): s_i = M_i r_i with
 // M_i = P^-1 or S_i P^-1 S_i, block partials of (r_i, s_i) into partial_i.

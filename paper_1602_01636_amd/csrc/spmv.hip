@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_g(const RowJob* __restrict__ jo
                                                    int njobs) {
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const RowJob& t = jobs[j];
-  if (*t.flag) return;
+  if (t.flag && *t.flag) return;
   row_body<3, P, R>(t.band, t.Ns, t.x, t.y, t.n1, t.n2, t.N, t.partial, -1, (int)blockIdx.x - start[j]);
 }
 
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const TileJob* __restrict__ jobs, const int* __restrict__ start, int njobs) {
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const TileJob& t = jobs[j];
-  if (*t.flag) return;
+  if (t.flag && *t.flag) return;
   tile_body<P, CH>(t.band, t.Ns, t.x, t.ext, t.n1, t.n2, t.n3, t.B2, t.B3, t.T2, (int)blockIdx.x - start[j]);
 }
 
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_combine_g(const CombineJob* __r
                                                            const int* __restrict__ start, int njobs) {
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const CombineJob& t = jobs[j];
-  if (*t.flag) return;
+  if (t.flag && *t.flag) return;
   combine_body(t.ext, t.x, t.y, t.n1, t.n2, t.n3, t.P, t.B2, t.B3, t.T2, t.T3, t.N, t.partial,
                (int)blockIdx.x - start[j]);
 }
@@ -770,7 +770,7 @@ igafd_status tile_g(int p, int ch, bool attr, const TileJob* jobs, const int* st
 
 igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const std::vector<igafd_ctx*>& cs,
                           const std::vector<const double*>& x, const std::vector<double*>& y,
-                          const std::vector<double*>& partial) {
+                          const std::vector<double*>& partial, bool stop_flags) {
   const int n = (int)cs.size();
   if (n == 0) return IGAFD_OK;
   // tiled problems: a launch per (degree, chunk count), the dynamic LDS the
@@ -815,7 +815,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
     for (int i : g.second) {
       igafd_ctx* c = cs[i];
       jobs.push_back(RowJob{c->band + c->halo, c->Ns, x[i], y[i], c->n[0], c->n[1], c->N, partial[i],
-                            &c->state->flag});
+                            stop_flags ? &c->state->flag : nullptr});
       start.push_back(start.back() + spmv_blocks(c));
     }
     const size_t oj = a.push(jobs.data(), sizeof(RowJob) * jobs.size());
@@ -835,7 +835,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
       const int B2 = c->tile_b2, B3 = c->tile_b3;
       const int T2 = (c->n[1] + B2 - 1) / B2, T3 = (c->n[2] + B3 - 1) / B3;
       jobs.push_back(TileJob{c->band + c->halo, c->Ns, x[i], c->ext, c->n[0], c->n[1], c->n[2], B2, B3, T2,
-                             &c->state->flag});
+                             stop_flags ? &c->state->flag : nullptr});
       start.push_back(start.back() + T2 * T3);
       lds = std::max(lds, sizeof(double) * ((size_t)(B2 + 2 * p) * (B3 + p) * c->n[0] + 2 * 64));
     }
@@ -858,7 +858,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
     const int B2 = c->tile_b2, B3 = c->tile_b3;
     const int T2 = (c->n[1] + B2 - 1) / B2, T3 = (c->n[2] + B3 - 1) / B3;
     cj.push_back(CombineJob{c->ext, x[i], y[i], c->n[0], c->n[1], c->n[2], c->p, B2, B3, T2, T3, c->N, partial[i],
-                            &c->state->flag});
+                            stop_flags ? &c->state->flag : nullptr});
     start.push_back(start.back() + (int)((c->N + kBlock - 1) / kBlock));
   }
   const size_t oj = a.push(cj.data(), sizeof(CombineJob) * cj.size());
