@@ -127,3 +127,51 @@ def test_batched_scaled_equals_individual(api):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_batched_edge_cases(api):
+    """A problem with b = 0 (stops at the start: no iteration, u = 0) among
+    others in the grouped batch, and a batch mixing 2D and 3D problems (the
+    stream-pool path): bitwise the single solves."""
+    import torch
+    probs = _batch_problems()[:3]
+    ctxs = [api.igafd_setup(pr) for pr in probs]
+    try:
+        bs, us, ref = [], [], []
+        for k, c in enumerate(ctxs):
+            b = torch.zeros(c.N, dtype=torch.float64, device="cuda")
+            if k != 1:
+                api.igafd_load_vector(c, synth.RHS_SINPROD, b)
+            u = torch.zeros_like(b)
+            info = api.igafd_solve(c, b, u)
+            ref.append((info, u.clone()))
+            bs.append(b)
+            us.append(torch.full_like(b, 2.0))
+        infos, _ = api.igafd_solve_batched(ctxs, bs, us)
+        assert infos[1]["iters"] == 0 and infos[1]["status"] == "OK" and not torch.any(us[1])
+        for (info_ref, u_ref), info, u in zip(ref, infos, us):
+            assert info["iters"] == info_ref["iters"]
+            assert torch.equal(u, u_ref)
+    finally:
+        for c in ctxs:
+            c.close()
+    mixed = [synth.uniform_problem(2, [20, 17], 3, geometry={"kind": "ring"}), _batch_problems()[0]]
+    ctxs = [api.igafd_setup(pr) for pr in mixed]
+    try:
+        bs, us, ref = [], [], []
+        for c in ctxs:
+            b = torch.zeros(c.N, dtype=torch.float64, device="cuda")
+            api.igafd_load_vector(c, synth.RHS_SINPROD, b)
+            u = torch.zeros_like(b)
+            info = api.igafd_solve(c, b, u)
+            ref.append((info, u.clone()))
+            bs.append(b)
+            us.append(torch.zeros_like(b))
+        infos, _ = api.igafd_solve_batched(ctxs, bs, us)
+        for (info_ref, u_ref), info, u in zip(ref, infos, us):
+            assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+            assert info["iters"] == info_ref["iters"]
+            assert torch.equal(u, u_ref)
+    finally:
+        for c in ctxs:
+            c.close()
