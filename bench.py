@@ -102,7 +102,8 @@ def spmv_kernel_name(api, ctx):
     s = api.igafd_get_shape(ctx)
     if s["tile_b2"] > 0:
         return (f"igafd_apply_A: k_copy (x into the zero-halo buffer) + k_spmv_tile<p={ctx.p}> "
-                f"({s['tile_b2']}x{s['tile_b3']} lines) + k_spmv_combine"), "tile"
+                f"({s['tile_b2']}x{s['tile_b3']} lines, {s['tile_threads']} threads) + k_spmv_combine"), \
+            f"tile {s['tile_b2']}x{s['tile_b3']}x{s['tile_threads']}"
     return f"igafd_apply_A: k_copy (x into the zero-halo buffer) + k_spmv<R={s['spmv_rows']}>", "row"
 
 
@@ -110,7 +111,8 @@ def profiled_traffic(kernel_tag, workload_tag):
     """HBM/fabric bytes per A product (one igafd_apply_A: the copy into the
     zero-halo buffer and the product kernels) from the committed counter
     summaries (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy),
-    used only while the A-product source is the one that was measured."""
+    used only while the A-product source and the kernel's launch shape (the
+    tag: tile lines x threads per block) are the ones that were measured."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1602_01636_amd", "csrc", "spmv.hip")
@@ -236,6 +238,20 @@ def copy_calibration(torch):
     log("copy calibration: 1 GiB read + 1 GiB written")
 
 
+def autotune(args, api, torch, ctx):
+    """igafd_autotune after setup (times the A-product candidates, among them
+    512-thread tiles, and the FD shapes on this problem): returns the seconds
+    it took, None when --no-autotune keeps the setup's shapes."""
+    if args.no_autotune:
+        return None
+    t0 = time.perf_counter()
+    api.igafd_autotune(ctx)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log(f"autotune {t:.2f}s: {api.igafd_get_shape(ctx)}")
+    return t
+
+
 def rhs(api, torch, synth, ctx):
     b = torch.zeros(ctx.N, dtype=torch.float64, device="cuda")
     api.igafd_load_vector(ctx, synth.RHS_SINPROD, b)
@@ -262,6 +278,7 @@ def run_ring(args, api, torch, synth):
     t_setup = time.perf_counter() - t0
     N, n = ctx.N, ctx.n[0]
     log(f"setup {t_setup:.2f}s N={N} nnz={ctx.nnz} band={ctx.band_bytes / 1e9:.2f} GB")
+    t_tune = autotune(args, api, torch, ctx)
     b = rhs(api, torch, synth, ctx)
     u = torch.zeros_like(b)
     t_all = time.perf_counter()
@@ -303,7 +320,7 @@ def run_ring(args, api, torch, synth):
         "iters": iters, "true_relres": infos[-1]["true_relres"],
         "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
         "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
-        "variants": variants, "setup_s": t_setup, "wall_s_timed": wall,
+        "variants": variants, "setup_s": t_setup, "autotune_s": t_tune, "wall_s_timed": wall,
         "solve_ms": {"median": 1e3 * float(np.median(times)), "min": 1e3 * min(times), "max": 1e3 * max(times)},
         "phases_ms": phases, "fd_share": fd_share,
         "paper_fd_share": {"value": 0.1309, "source": "Table percentage, revolved ring h^-1 = 128, p = 3, "
@@ -323,6 +340,7 @@ def run_warped(args, api, torch, synth):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup:.2f}s N={ctx.N} nnz={ctx.nnz} band={ctx.band_bytes / 1e9:.2f} GB")
+    t_tune = autotune(args, api, torch, ctx)
     b = rhs(api, torch, synth, ctx)
     u = torch.zeros_like(b)
     ts64, inf64 = timed_solves(api, torch, ctx, b, u, max(2, args.steps // 2), 1)
@@ -348,7 +366,8 @@ def run_warped(args, api, torch, synth):
         "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"], "rel_err_vs_fp64": err,
         "precond_applies_per_s": {pr: 1e3 / t for pr, t in kr["t_fd"].items()},
         "kernel_ms": {"spmv": kr["t_spmv"], **{f"fd_{pr}": t for pr, t in kr["t_fd"].items()}},
-        "variants": variants, "setup_s": t_setup, "roofline": roofline(kr), "fd_roofline": fd_roofline(kr, "bf16"),
+        "variants": variants, "setup_s": t_setup, "autotune_s": t_tune, "roofline": roofline(kr),
+        "fd_roofline": fd_roofline(kr, "bf16"),
         "cpu_baseline": None})
     ctx.close()
     return out
@@ -427,6 +446,7 @@ def run_learned(args, api, torch, synth):
         torch.cuda.synchronize()
         t_feat.append(time.perf_counter() - t0)
     t_setup_plain, t_setup_feat = float(np.median(t_plain)), float(np.median(t_feat))
+    t_tune = autotune(args, api, torch, ctx)
     b = rhs(api, torch, synth, ctx)
     u = torch.zeros_like(b)
     res = {}
@@ -460,7 +480,7 @@ def run_learned(args, api, torch, synth):
                             f"warped cubes)", "elements": E, "degree": p, "N": ctx.N}
     out = result(args, ms_per_step / 1e3, ms_per_step, "f64 (network bf16, fp32 accumulation)", workload, {
         "iters": infos[-1]["iters"], "variants": res, "train_s": t_train, "train_dofs": total,
-        "loss_first_last": [hist[0], hist[-1]], "roofline": roofline(kr), "cpu_baseline": None})
+        "loss_first_last": [hist[0], hist[-1]], "autotune_s": t_tune, "roofline": roofline(kr), "cpu_baseline": None})
     ctx.close()
     mlp.close()
     return out
@@ -802,6 +822,8 @@ def main():
     ap.add_argument("--train", type=int, default=2000, help="training problems (learned workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the setup's default kernel shapes (ring, warped, learned workloads)")
     ap.add_argument("--no-extras", action="store_true",
                     help="ring workload only: skip the warped-cube BF16 and learned-scaling sub-objects")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -224,17 +224,20 @@ igafd_status igafd_solve_batched(igafd_ctx* const* ctxs, int count, const double
  * products, 1..8) and spmv_rows (rows per thread of the row-parallel A
  * product: 1, 2, 4; a nonzero value selects that kernel instead of the 3D
  * tiled one).  Zero for both: time the candidates on this problem (row
- * counts and tile shapes) and keep the fastest; may allocate the tile
- * buffer, so call it at setup time, not inside a timed or captured region. */
+ * counts, and tile shapes at 256 and 512 threads per block) and keep the
+ * fastest (a later candidate must win by 1%, so near-ties resolve the same
+ * way each time); may allocate the tile buffer, so call it at setup time,
+ * not inside a timed or captured region. */
 igafd_status igafd_autotune(igafd_ctx* ctx, int fd_tiles, int spmv_rows);
 
 /* Kernel shape in use (host outputs, any may be NULL): tile_b2, tile_b3 = the
  * lines per tile of the 3D tiled A product (0 when the row-parallel kernel
- * with spmv_rows rows per thread is used); fd_fused = 1 when the 3D FD apply
- * runs as three fused passes, fd_tiles = row tiles per wave of the generic
- * mode products otherwise. */
+ * with spmv_rows rows per thread is used) and tile_threads its threads per
+ * block (256 or 512); fd_fused = 1 when the 3D FD apply runs as three fused
+ * passes, fd_tiles = row tiles per wave of the generic mode products
+ * otherwise. */
 igafd_status igafd_get_shape(const igafd_ctx* ctx, int* spmv_rows, int* tile_b2, int* tile_b3, int* fd_fused,
-                             int* fd_tiles);
+                             int* fd_tiles, int* tile_threads);
 
 /* Diagonals of A and P (N doubles each, device; either may be NULL). */
 igafd_status igafd_diagonals(igafd_ctx* ctx, double* diagA_dev, double* diagP_dev);

@@ -87,7 +87,7 @@ _SIGNATURES = {
     "igafd_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(igafd_solve_opts),
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "igafd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
-    "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 5),
+    "igafd_get_shape": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int)] * 6),
     "igafd_spectral_bounds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]),
     "igafd_scaling_gate": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double),
@@ -416,10 +416,11 @@ def igafd_scaling_gate(ctx: Context, gain=2.0):
 
 
 def igafd_get_shape(ctx: Context) -> dict:
-    """Kernel shape in use: {"spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles"}."""
-    v = [C.c_int() for _ in range(5)]
+    """Kernel shape in use: {"spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles", "tile_threads"}."""
+    v = [C.c_int() for _ in range(6)]
     _check(lib().igafd_get_shape(_h(ctx), *[C.byref(x) for x in v]))
-    return dict(zip(("spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles"), [x.value for x in v]))
+    return dict(zip(("spmv_rows", "tile_b2", "tile_b3", "fd_fused", "fd_tiles", "tile_threads"),
+                    [x.value for x in v]))
 
 
 def igafd_get_eigen(ctx: Context, direction: int):

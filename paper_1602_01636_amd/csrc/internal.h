@@ -120,6 +120,7 @@ struct igafd_ctx {
   long long nnz = 0;
   int spmv_rows = 2;                       // rows per thread of the row-parallel A product
   int tile_b2 = 0, tile_b3 = 0;            // 3D tiled A product: lines per tile (0: row-parallel kernel)
+  int tile_tb = 256;                       // its threads per block (256: two blocks per CU; 512: one)
   double* ext = nullptr;                   // per-tile extended accumulators of the tiled product
   long long ext_cap = 0;                   // doubles allocated at ext
   int fd_tiles = 2;                        // 16-row tiles per wave in the mode products
@@ -177,8 +178,8 @@ igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* q
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
 int spmv_blocks(const igafd_ctx* c);
-bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3);
-igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3);
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3, int tb = 256);
+igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3, int tb = 256);
 igafd_status mask_hole(igafd_ctx* c, double* y);
 // fd.hip
 igafd_status fd_apply(igafd_ctx* c, int prec, const double* r, double* s, const double* scaling,

@@ -18,6 +18,7 @@
 // reduction tree: deterministic).
 #include <algorithm>
 #include <map>
+#include <tuple>
 
 #include "internal.h"
 #include "reduce.h"
@@ -177,7 +178,7 @@ constexpr int kTileMaxChP[kMaxDegree + 1] = {0, 8, 8, 8, 4, 1, 1};
 constexpr int kXsRegMaxChP[kMaxDegree + 1] = {0, 8, 4, 5, 2, 1, 1};
 
 // chunks of 256 row pairs of a B2 x B3 tile
-inline int tile_chunks(int b2, int b3, int n1) { return ((b2 * b3 * n1 + 1) / 2 + kBlock - 1) / kBlock; }
+inline int tile_chunks(int b2, int b3, int n1, int tb = kBlock) { return ((b2 * b3 * n1 + 1) / 2 + tb - 1) / tb; }
 
 typedef const __attribute__((address_space(1))) char* gbytes;  // global memory, byte addressed
 typedef double d2_t __attribute__((ext_vector_type(2)));
@@ -291,8 +292,8 @@ __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restri
 // q = threadIdx.x + 256 m of the tile: rows 2q, 2q+1 of the concatenated runs.
 // The LDS tile allows about two blocks per CU: the occupancy target lets the
 // scheduler keep a chunk's loads in flight together.
-// tile_body: the work of tile `tile` (t2 fastest).
-template <int P, int CH>
+// tile_body: the work of tile `tile` (t2 fastest) by TB threads.
+template <int P, int CH, int TB>
 __device__ __forceinline__ void tile_body(const double* __restrict__ band, long long Ns, const double* __restrict__ x,
                                           double* __restrict__ ext, int n1, int n2, int n3, int B2, int B3, int T2,
                                           int tile) {
@@ -301,7 +302,7 @@ __device__ __forceinline__ void tile_body(const double* __restrict__ band, long 
   const int elems = E2 * E3 * n1;
   const int t2 = tile % T2, t3 = tile / T2;
   const int a0 = t2 * B2, c0 = t3 * B3;
-  for (int k = threadIdx.x; k < elems; k += kBlock) lds[k] = 0.0;
+  for (int k = threadIdx.x; k < elems; k += TB) lds[k] = 0.0;
   const int run = B2 * n1;                                  // rows of one run (even)
   const int valid_run = (n2 - a0 < B2 ? n2 - a0 : B2) * n1;  // rows of a run inside the grid
   const long long n12 = (long long)n1 * n2;
@@ -311,7 +312,7 @@ __device__ __forceinline__ void tile_body(const double* __restrict__ band, long 
   unsigned own = 0;  // bits 2m, 2m+1: rows of chunk m with an accumulator slot
 #pragma unroll
   for (int m = 0; m < CH; ++m) {
-    const int r = 2 * (threadIdx.x + kBlock * m);  // first row of the pair in the tile
+    const int r = 2 * (threadIdx.x + TB * m);  // first row of the pair in the tile
     const int j = r / run, off = r - j * run;       // run (= b3) and row in the run
     const bool ok0 = j < B3 && c0 + j < n3 && off < valid_run;
     const bool ok1 = ok0 && off + 1 < valid_run;
@@ -355,15 +356,16 @@ __device__ __forceinline__ void tile_body(const double* __restrict__ band, long 
   // streaming stores: the tile buffer is read once, by k_spmv_combine (regular
   // stores made the kernel 4-6% slower at p = 3..5)
   double* out = ext + (long long)tile * elems;
-  for (int k = threadIdx.x; k < elems; k += kBlock) __builtin_nontemporal_store(lds[k], out + k);
+  for (int k = threadIdx.x; k < elems; k += TB) __builtin_nontemporal_store(lds[k], out + k);
 }
 
-template <int P, int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile(
+// TB = 256: two blocks per CU (LDS permitting); TB = 512: one larger tile per CU
+template <int P, int CH, int TB>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile(
     const double* __restrict__ band, long long Ns, const double* __restrict__ x, double* __restrict__ ext, int n1,
     int n2, int n3, int B2, int B3, int T2, const int* __restrict__ flag) {
   if (flag && *flag) return;
-  tile_body<P, CH>(band, Ns, x, ext, n1, n2, n3, B2, B3, T2, (int)blockIdx.x);
+  tile_body<P, CH, TB>(band, Ns, x, ext, n1, n2, n3, B2, B3, T2, (int)blockIdx.x);
 }
 
 // Grouped form: the tiles of several problems in one launch (block b works on
@@ -377,13 +379,13 @@ struct TileJob {
   const int* flag;
 };
 
-template <int P, int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile_g(
+template <int P, int CH, int TB>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_spmv_tile_g(
     const TileJob* __restrict__ jobs, const int* __restrict__ start, int njobs) {
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const TileJob& t = jobs[j];
   if (t.flag && *t.flag) return;
-  tile_body<P, CH>(t.band, t.Ns, t.x, t.ext, t.n1, t.n2, t.n3, t.B2, t.B3, t.T2, (int)blockIdx.x - start[j]);
+  tile_body<P, CH, TB>(t.band, t.Ns, t.x, t.ext, t.n1, t.n2, t.n3, t.B2, t.B3, t.T2, (int)blockIdx.x - start[j]);
 }
 
 __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
@@ -475,13 +477,13 @@ igafd_status launch_r(igafd_ctx* c, const double* xpad, double* y, double* parti
 
 // Dynamic LDS above 64 KB needs the kernel attribute; set once when a tile
 // shape is selected (never inside a launch sequence that may be captured).
-template <int P>
-igafd_status tile_lds_attr(int ch, int lds) {
+template <int P, int TB>
+igafd_status tile_lds_attr_tb(int ch, int lds) {
   const void* fn = nullptr;
   switch (ch) {
 #define IGAFD_CH(K)                              \
   case K:                                        \
-    fn = (const void*)&k_spmv_tile<P, K>;        \
+    fn = (const void*)&k_spmv_tile<P, K, TB>;    \
     break;
     IGAFD_CH(1) IGAFD_CH(2) IGAFD_CH(3) IGAFD_CH(4) IGAFD_CH(5) IGAFD_CH(6) IGAFD_CH(7) IGAFD_CH(8)
 #undef IGAFD_CH
@@ -493,12 +495,22 @@ igafd_status tile_lds_attr(int ch, int lds) {
   return IGAFD_OK;
 }
 
+template <int P>
+igafd_status tile_lds_attr(int ch, int lds, int tb) {
+  return tb == 512 ? tile_lds_attr_tb<P, 512>(ch, lds) : tile_lds_attr_tb<P, 256>(ch, lds);
+}
+
 template <int P, int CH>
 igafd_status launch_tile_ch(igafd_ctx* c, const double* xpad, int T2, size_t lds, const int* flag) {
   const int T3 = (c->n[2] + c->tile_b3 - 1) / c->tile_b3;
-  hipLaunchKernelGGL((k_spmv_tile<P, CH>), dim3((unsigned)(T2 * T3)), dim3(kBlock), lds, c->stream,
-                     c->band + c->halo, c->Ns, xpad, c->ext, c->n[0], c->n[1], c->n[2], c->tile_b2, c->tile_b3, T2,
-                     flag);
+  if (c->tile_tb == 512)
+    hipLaunchKernelGGL((k_spmv_tile<P, CH, 512>), dim3((unsigned)(T2 * T3)), dim3(512), lds, c->stream,
+                       c->band + c->halo, c->Ns, xpad, c->ext, c->n[0], c->n[1], c->n[2], c->tile_b2, c->tile_b3, T2,
+                       flag);
+  else
+    hipLaunchKernelGGL((k_spmv_tile<P, CH, 256>), dim3((unsigned)(T2 * T3)), dim3(256), lds, c->stream,
+                       c->band + c->halo, c->Ns, xpad, c->ext, c->n[0], c->n[1], c->n[2], c->tile_b2, c->tile_b3, T2,
+                       flag);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
@@ -510,7 +522,7 @@ igafd_status launch_tile(igafd_ctx* c, const double* xpad, double* y, double* pa
   const int T2 = (n2 + B2 - 1) / B2, T3 = (n3 + B3 - 1) / B3;
   const int E2 = B2 + 2 * P, E3 = B3 + P;
   const size_t lds = sizeof(double) * ((size_t)E2 * E3 * n1 + 2 * 64);
-  const int ch = tile_chunks(B2, B3, n1);
+  const int ch = tile_chunks(B2, B3, n1, c->tile_tb);
   if ((long long)T2 * T3 * E2 * E3 * n1 > c->ext_cap || ch < 1 || ch > kTileMaxCh) {
     set_error("internal: tile shape does not fit the tile buffer");
     return IGAFD_ERR_ARG;
@@ -552,8 +564,9 @@ int spmv_blocks(const igafd_ctx* c) {
 // accumulator value written), (row pairs / lanes of the chunks: lane use) and
 // (tiles / resident-block slots of the rounds the grid takes: tail of the
 // grid).  Returns false when no shape fits (or the problem is 2D or too large
-// for 32-bit row offsets): the row-parallel kernel is used then.
-bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out) {
+// for 32-bit row offsets): the row-parallel kernel is used then.  tb: threads
+// per block (256: up to two blocks per CU; 512: one).
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out, int tb) {
   if (c->dim != 3 || c->N >= (1LL << 29)) return false;  // byte offsets of rows fit 32 bits
   const int p = c->p, n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
   int dev = 0, cus = 256, lds_cu = 160 * 1024;
@@ -566,15 +579,15 @@ bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b
     for (int b2 = 1; b2 <= 32 && b2 <= n2; ++b2) {
       const int lines = b2 * b3;
       if (lines < 2) continue;
-      const int ch = tile_chunks(b2, b3, n1);
+      const int ch = tile_chunks(b2, b3, n1, tb);
       if ((b2 * n1) % 2 != 0 || ch > kTileMaxChP[p]) continue;
       const long long e = (long long)(b2 + 2 * p) * (b3 + p);
       const long long lds = 8 * (e * n1 + 128);
       if (lds > lds_limit) continue;
       const long long tiles = (long long)((n2 + b2 - 1) / b2) * ((n3 + b3 - 1) / b3);
-      const long long slots = (long long)cus * std::max(1LL, (long long)lds_cu / lds);
+      const long long slots = (long long)cus * (tb == 512 ? 1LL : std::max(1LL, (long long)lds_cu / lds));
       const long long rounds = (tiles + slots - 1) / slots;
-      double score = (double)lines / (double)e * ((double)lines * n1 / 2.0 / (ch * kBlock)) *
+      double score = (double)lines / (double)e * ((double)lines * n1 / 2.0 / ((double)ch * tb)) *
                      ((double)tiles / (double)(rounds * slots));
       // shapes that keep the own-row x window in registers issue fewer loads
       // per line offset (p = 4, 112^3: 4 x 2 lines 887 us against 4 x 3, 968 us)
@@ -588,15 +601,17 @@ bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b
   return best > 0.0;
 }
 
-// Select a tile shape (b2 = 0: the row-parallel kernel) and make the tile
-// buffer large enough (setup-time allocation only).
-igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3) {
+// Select a tile shape (b2 = 0: the row-parallel kernel) and its threads per
+// block (256 or 512), and make the tile buffer large enough (setup-time
+// allocation only).
+igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3, int tb) {
   if (b2 <= 0) {
     c->tile_b2 = c->tile_b3 = 0;
+    c->tile_tb = 256;
     return IGAFD_OK;
   }
-  if (c->dim != 3 || b3 <= 0 || b2 > c->n[1] || b3 > c->n[2] || (b2 * c->n[0]) % 2 != 0 ||
-      tile_chunks(b2, b3, c->n[0]) > kTileMaxChP[c->p] || c->N >= (1LL << 29)) {
+  if (c->dim != 3 || b3 <= 0 || b2 > c->n[1] || b3 > c->n[2] || (b2 * c->n[0]) % 2 != 0 || (tb != 256 && tb != 512) ||
+      tile_chunks(b2, b3, c->n[0], tb) > kTileMaxChP[c->p] || c->N >= (1LL << 29)) {
     set_error("tile shape not usable for this problem");
     return IGAFD_ERR_ARG;
   }
@@ -612,12 +627,12 @@ igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3) {
     return IGAFD_ERR_ARG;
   }
   if (lds > 65536) {
-    const int ch = tile_chunks(b2, b3, c->n[0]);
+    const int ch = tile_chunks(b2, b3, c->n[0], tb);
     igafd_status s = IGAFD_OK;
     switch (p) {
 #define IGAFD_TCASE(P)                          \
   case P:                                       \
-    s = tile_lds_attr<P>(ch, (int)lds);         \
+    s = tile_lds_attr<P>(ch, (int)lds, tb);     \
     break;
       IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
 #undef IGAFD_TCASE
@@ -636,6 +651,7 @@ igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3) {
   }
   c->tile_b2 = b2;
   c->tile_b3 = b3;
+  c->tile_tb = tb;
   return IGAFD_OK;
 }
 
@@ -691,29 +707,37 @@ bool spmv_groupable(const igafd_ctx* c) { return c->dim == 3 && c->p >= 1 && c->
 
 namespace {
 
-template <int P, int CH>
+template <int P, int CH, int TB>
 igafd_status tile_g_launch(const TileJob* jobs, const int* start, int njobs, int blocks, size_t lds,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv_tile_g<P, CH>), dim3((unsigned)blocks), dim3(kBlock), lds, st, jobs, start, njobs);
+  hipLaunchKernelGGL((k_spmv_tile_g<P, CH, TB>), dim3((unsigned)blocks), dim3(TB), lds, st, jobs, start, njobs);
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
 
-template <int P, int CH>
+template <int P, int CH, int TB>
 igafd_status tile_g_attr(size_t lds) {
-  IGAFD_HIP_CHECK(hipFuncSetAttribute((const void*)k_spmv_tile_g<P, CH>,
+  IGAFD_HIP_CHECK(hipFuncSetAttribute((const void*)k_spmv_tile_g<P, CH, TB>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return IGAFD_OK;
 }
 
-// (p, chunk count) -> the grouped tile kernel's launch or attribute call
+template <int P, int CH>
+igafd_status tile_g_tb(int tb, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks, size_t lds,
+                       hipStream_t st) {
+  if (tb == 512) return attr ? tile_g_attr<P, CH, 512>(lds) : tile_g_launch<P, CH, 512>(jobs, start, njobs, blocks, lds, st);
+  return attr ? tile_g_attr<P, CH, 256>(lds) : tile_g_launch<P, CH, 256>(jobs, start, njobs, blocks, lds, st);
+}
+
+// (p, chunk count, threads per block) -> the grouped tile kernel's launch or
+// attribute call
 template <int P>
-igafd_status tile_g_dispatch(int ch, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks,
+igafd_status tile_g_dispatch(int ch, int tb, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks,
                              size_t lds, hipStream_t st) {
   switch (ch) {
 #define IGAFD_CH(K) \
   case K:           \
-    return attr ? tile_g_attr<P, K>(lds) : tile_g_launch<P, K>(jobs, start, njobs, blocks, lds, st);
+    return tile_g_tb<P, K>(tb, attr, jobs, start, njobs, blocks, lds, st);
     IGAFD_CH(1) IGAFD_CH(2) IGAFD_CH(3) IGAFD_CH(4) IGAFD_CH(5) IGAFD_CH(6) IGAFD_CH(7) IGAFD_CH(8)
 #undef IGAFD_CH
     default:
@@ -752,12 +776,12 @@ igafd_status row_g(int p, int r, const RowJob* jobs, const int* start, int njobs
   }
 }
 
-igafd_status tile_g(int p, int ch, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks, size_t lds,
-                    hipStream_t st) {
+igafd_status tile_g(int p, int ch, int tb, bool attr, const TileJob* jobs, const int* start, int njobs, int blocks,
+                    size_t lds, hipStream_t st) {
   switch (p) {
 #define IGAFD_TCASE(P) \
   case P:              \
-    return tile_g_dispatch<P>(ch, attr, jobs, start, njobs, blocks, lds, st);
+    return tile_g_dispatch<P>(ch, tb, attr, jobs, start, njobs, blocks, lds, st);
     IGAFD_TCASE(1) IGAFD_TCASE(2) IGAFD_TCASE(3) IGAFD_TCASE(4) IGAFD_TCASE(5) IGAFD_TCASE(6)
 #undef IGAFD_TCASE
     default:
@@ -776,7 +800,8 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
   // tiled problems: a launch per (degree, chunk count), the dynamic LDS the
   // largest accumulator of the group, then one combine launch; row-parallel
   // problems: a launch per (degree, rows per thread)
-  std::map<std::pair<int, int>, std::vector<int>> tgroups, rgroups;
+  std::map<std::pair<int, int>, std::vector<int>> rgroups;
+  std::map<std::tuple<int, int, int>, std::vector<int>> tgroups;  // (degree, chunks, threads per block)
   std::vector<int> tiled;
   for (int i = 0; i < n; ++i) {
     const igafd_ctx* c = cs[i];
@@ -786,7 +811,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
     }
     const int p = c->p;
     if (c->tile_b2 > 0) {
-      const int ch = tile_chunks(c->tile_b2, c->tile_b3, c->n[0]);
+      const int ch = tile_chunks(c->tile_b2, c->tile_b3, c->n[0], c->tile_tb);
       const long long T2 = (c->n[1] + c->tile_b2 - 1) / c->tile_b2, T3 = (c->n[2] + c->tile_b3 - 1) / c->tile_b3;
       if (T2 * T3 * (c->tile_b2 + 2 * p) * (c->tile_b3 + p) * (long long)c->n[0] > c->ext_cap || ch < 1 ||
           ch > kTileMaxCh) {
@@ -797,7 +822,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
         set_error("internal: A-product grid larger than the partial-sum buffer");
         return IGAFD_ERR_ARG;
       }
-      tgroups[{p, ch}].push_back(i);
+      tgroups[std::make_tuple(p, ch, c->tile_tb)].push_back(i);
       tiled.push_back(i);
     } else {
       const int R = (c->spmv_rows == 1 || c->spmv_rows == 4) ? c->spmv_rows : 2;
@@ -826,7 +851,7 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
     });
   }
   for (const auto& g : tgroups) {
-    const int p = g.first.first, ch = g.first.second;
+    const int p = std::get<0>(g.first), ch = std::get<1>(g.first), tb = std::get<2>(g.first);
     std::vector<TileJob> jobs;
     std::vector<int> start(1, 0);
     size_t lds = 0;
@@ -840,14 +865,14 @@ igafd_status spmv_grouped(GroupArena& a, std::vector<GroupStep>& steps, const st
       lds = std::max(lds, sizeof(double) * ((size_t)(B2 + 2 * p) * (B3 + p) * c->n[0] + 2 * 64));
     }
     if (lds > 65536) {
-      const igafd_status sa = tile_g(p, ch, true, nullptr, nullptr, 0, 0, lds, nullptr);
+      const igafd_status sa = tile_g(p, ch, tb, true, nullptr, nullptr, 0, 0, lds, nullptr);
       if (sa != IGAFD_OK) return sa;
     }
     const size_t oj = a.push(jobs.data(), sizeof(TileJob) * jobs.size());
     const size_t os = a.push(start.data(), sizeof(int) * start.size());
     const int nj = (int)jobs.size(), blocks = start.back();
-    steps.push_back([&a, p, ch, oj, os, nj, blocks, lds](hipStream_t st) {
-      return tile_g(p, ch, false, a.at<TileJob>(oj), a.at<int>(os), nj, blocks, lds, st);
+    steps.push_back([&a, p, ch, tb, oj, os, nj, blocks, lds](hipStream_t st) {
+      return tile_g(p, ch, tb, false, a.at<TileJob>(oj), a.at<int>(os), nj, blocks, lds, st);
     });
   }
   if (tiled.empty()) return IGAFD_OK;

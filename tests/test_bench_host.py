@@ -38,7 +38,10 @@ def test_committed_counter_summary_matches_the_a_product_source():
     a changed source without re-taken counters would report null."""
     sys.path.insert(0, ROOT)
     import bench
-    traffic, source = bench.profiled_traffic("tile", "thick_ring E=128 p=3")
+    summary = os.path.join(ROOT, "profiles", "k_spmv_tile__thick_ring_128_p3__hbm_counters.md")
+    tag = [ln.split(": ", 1)[1].strip() for ln in open(summary) if ln.strip().startswith("traffic_kernel: ")][0]
+    assert tag.startswith("tile ")  # tile lines and threads per block of the measured launch
+    traffic, source = bench.profiled_traffic(tag, "thick_ring E=128 p=3")
     assert source is not None and source.startswith("profiles")
     # one igafd_apply_A moves more than its algorithmic bytes (x once, each stored value once)
     E, p = 128, 3

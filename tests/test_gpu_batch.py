@@ -59,6 +59,38 @@ def test_batched_equals_individual(api, graph, grouped, monkeypatch):
         c.close()
 
 
+def test_batched_mixed_tile_blocks_equals_individual(api, monkeypatch):
+    """Problems whose tiled A products run 512-thread blocks next to ones with
+    256 (separate grouped launches): bitwise the single solves."""
+    import torch
+    probs = _batch_problems()
+    ctxs = []
+    for k, pr in enumerate(probs):
+        if k % 2 == 0:
+            monkeypatch.setenv("IGAFD_SPMV_TILE", "2x2x512")
+        else:
+            monkeypatch.delenv("IGAFD_SPMV_TILE", raising=False)
+        ctxs.append(api.igafd_setup(pr))
+    threads = [api.igafd_get_shape(c)["tile_threads"] for c in ctxs]
+    assert threads[0::2] == [512] * 3 and all(t == 256 for t in threads[1::2])
+    bs, us, ref = [], [], []
+    for c in ctxs:
+        b = torch.zeros(c.N, dtype=torch.float64, device="cuda")
+        api.igafd_load_vector(c, synth.RHS_SINPROD, b)
+        u = torch.zeros_like(b)
+        info = api.igafd_solve(c, b, u)
+        ref.append((info, u.clone()))
+        bs.append(b)
+        us.append(torch.zeros_like(b))
+    infos, _ = api.igafd_solve_batched(ctxs, bs, us)
+    for (info_ref, u_ref), info, u in zip(ref, infos, us):
+        assert info["status"] == "OK" and info["true_relres"] <= 1e-8
+        assert info["iters"] == info_ref["iters"]
+        assert torch.equal(u, u_ref)
+    for c in ctxs:
+        c.close()
+
+
 def test_batched_split_bf16_equals_individual(api):
     """The batched (graph-captured) path with split-BF16 applies in the
     flexible CG: bitwise the individual solves, converged in FP64."""

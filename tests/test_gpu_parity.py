@@ -61,10 +61,13 @@ def test_apply_A_matches_oracle(api, name, prob, rng):
 
 
 TILE_CASES = [
-    # (problem, tile shape "b2xb3" or "0" for the row-parallel kernel)
+    # (problem, tile shape "b2xb3[xthreads]" or "0" for the row-parallel kernel)
     ("3d_warped_kappa_p3", "4x1"), ("3d_warped_kappa_p3", "2x2"), ("3d_warped_kappa_p3", "4x4"),
     ("3d_warped_kappa_p3", "0"), ("3d_ring_p2", "8x1"), ("3d_ring_p2", "2x6"), ("3d_identity_p1", "4x3"),
     ("3d_warped_p5", "2x2"), ("3d_warped_p5", "0"), ("long_n1_p3", "4x4"), ("long_n1_p3", "0"),
+    # 512 threads per block (one block per CU, larger tiles)
+    ("3d_warped_kappa_p3", "4x4x512"), ("3d_ring_p2", "2x6x512"), ("3d_warped_p5", "2x2x512"),
+    ("long_n1_p3", "4x4x512"),
 ]
 
 
@@ -83,6 +86,10 @@ def test_apply_A_kernel_shapes(api, name, tile, rng, monkeypatch):
     with api.igafd_setup(prob) as ctx:
         x = rng.standard_normal(ctx.N)
         y = to_dev(np.zeros(ctx.N))
+        if "x" in tile:
+            shape = api.igafd_get_shape(ctx)
+            want = [int(v) for v in tile.split("x")] + [256]
+            assert (shape["tile_b2"], shape["tile_b3"], shape["tile_threads"]) == tuple(want[:3])
         api.igafd_apply_A(ctx, to_dev(x), y)
         scale = abs(A) @ np.abs(x)
         assert np.max(np.abs(to_host(y) - A @ x) / scale) < 1e-12
