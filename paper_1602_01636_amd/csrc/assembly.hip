@@ -144,40 +144,44 @@ __device__ void feature_sums(int ch0, const double* vals, const double (*sV)[P +
     F2[idx] = s;
   }
   __syncthreads();
-  // the sums of a thread first, then all their loads before any store
-  // (distinct rows and channels)
-  constexpr int ITEMS = NCH * L * L * L3, PER = (ITEMS + kBlock - 1) / kBlock;
-  double sv[PER];
-  long long off[PER];  // -1: not a dof
+  // one thread per local function: its NCH channel sums, then one
+  // read-modify-write of the NCH consecutive doubles of its row (a 32- or
+  // 64-byte run, instead of NCH scattered 8-byte accesses from as many waves)
+  static_assert(NCH % 4 == 0, "channel quadruples");
+  typedef double dpair __attribute__((ext_vector_type(2)));
+  constexpr int DOFS = L * L * L3, PER = (DOFS + kBlock - 1) / kBlock;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    off[k] = -1;
-    sv[k] = 0.0;
-    const int idx = tid + k * kBlock;
-    if (idx >= ITEMS) continue;
-    const int c = idx / (L * L * L3), r = idx % (L * L * L3);
+    const int r = tid + k * kBlock;
+    if (r >= DOFS) break;
     const int a1 = r % L, a2 = (r / L) % L, a3 = r / (L * L);
     const int r1 = first[0] + a1 - 1, r2 = first[1] + a2 - 1, r3 = (D == 3) ? first[2] + a3 - 1 : 0;
     if (r1 < 0 || r1 >= T.n[0] || r2 < 0 || r2 >= T.n[1] || r3 < 0 || r3 >= T.n[2]) continue;
-    double s = 0.0;
+    dpair* row = reinterpret_cast<dpair*>(acc + 8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)) + ch0);
+    // four channels at a time (the registers of eight sums and their old
+    // values would cost the p = 4 assembly a wave per SIMD)
 #pragma unroll
-    for (int t3 = 0; t3 < Q3; ++t3) s += sV[2][t3][a3] * F2[c * (L * L * Q3) + (t3 * L + a2) * L + a1];
-    off[k] = 8 * (r1 + (long long)T.n[0] * (r2 + (long long)T.n[1] * r3)) + ch0 + c;
-    sv[k] = s;
+    for (int h = 0; h < NCH; h += 4) {
+      const dpair o0 = row[h / 2], o1 = row[h / 2 + 1];
+      double sv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int t3 = 0; t3 < Q3; ++t3) s += sV[2][t3][a3] * F2[(h + c) * (L * L * Q3) + (t3 * L + a2) * L + a1];
+        sv[c] = s;
+      }
+      row[h / 2] = dpair{o0.x + sv[0], o0.y + sv[1]};
+      row[h / 2 + 1] = dpair{o1.x + sv[2], o1.y + sv[3]};
+    }
   }
-  double old[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) old[k] = off[k] >= 0 ? acc[off[k]] : 0.0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k)
-    if (off[k] >= 0) acc[off[k]] = old[k] + sv[k];
   __syncthreads();
 }
 
 // FEAT = 1: also the per-dof feature sums of the learned scaling into acc
 // (8 doubles per dof), from the same Gauss-point evaluation of the map.
 template <int D, int P, int FEAT>
-__global__ __launch_bounds__(kBlock) void k_assemble(Tables T, GeomDesc g, double* __restrict__ band,
+__global__ __launch_bounds__(kBlock, (D == 3 && P <= 4) ? 5 : 1) void k_assemble(Tables T, GeomDesc g, double* __restrict__ band,
                                                      long long Ns, int c1, int c2, int c3, int m1, int m2,
                                                      int* __restrict__ err, double* __restrict__ acc) {
   constexpr int Q = P + 1, L = P + 1;
