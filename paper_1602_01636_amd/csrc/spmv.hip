@@ -392,25 +392,46 @@ __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b :
 
 // y[i] = sum over the tiles whose extended region holds row i (t3, then t2
 // ascending); optional per-block partial of (x, y).  Block bx of the rows.
+// Per row, the tiles whose extended region covers it: t3 in [t3lo, t3hi] and
+// t2 in [t2lo, t2hi]; their accumulator values are added in the order t3, t2
+// ascending.  M3, M2 > 0: at most M3 x M2 covering tiles (the launch's tile
+// shape guarantees it), all of their loads issued before the first add
+// (slots past the row's range read a covered tile and are skipped by a
+// select, so the sum and its order are those of the loop); 0, 0: the loop.
+template <int M3, int M2>
 __device__ __forceinline__ void combine_body(const double* __restrict__ ext, const double* __restrict__ x,
                                              double* __restrict__ y, int n1, int n2, int n3, int P, int B2, int B3,
                                              int T2, int T3, long long N, double* __restrict__ partial, int bx) {
   const long long i = (long long)bx * kBlock + threadIdx.x;
   double dot = 0.0;
   if (i < N) {
-    const int i1 = (int)(i % n1);
-    const long long rest = i / n1;
-    const int i2 = (int)(rest % n2), i3 = (int)(rest / n2);
+    // 32-bit index arithmetic: the tiled product needs N < 2^29
+    const unsigned iu = (unsigned)i, rest = iu / (unsigned)n1;
+    const int i1 = (int)(iu - rest * (unsigned)n1);
+    const int i3 = (int)(rest / (unsigned)n2), i2 = (int)(rest - (unsigned)i3 * (unsigned)n2);
     const int E2 = B2 + 2 * P, E3 = B3 + P;
     const long long elems = (long long)E2 * E3 * n1;
     const int t3lo = max(0, ceil_div(i3 - E3 + 1, B3)), t3hi = min(T3 - 1, i3 / B3);
     const int t2lo = max(0, ceil_div(i2 - B2 - P + 1, B2)), t2hi = min(T2 - 1, (i2 + P) / B2);
+    auto at = [&](int t3, int t2) {
+      const int line = (i3 - t3 * B3) * E2 + (i2 - t2 * B2 + P);
+      return ext[((long long)t3 * T2 + t2) * elems + (long long)line * n1 + i1];
+    };
     double s = 0.0;
-    for (int t3 = t3lo; t3 <= t3hi; ++t3)
-      for (int t2 = t2lo; t2 <= t2hi; ++t2) {
-        const int line = (i3 - t3 * B3) * E2 + (i2 - t2 * B2 + P);
-        s += ext[((long long)t3 * T2 + t2) * elems + (long long)line * n1 + i1];
-      }
+    if constexpr (M3 > 0) {
+      double v[M3][M2];
+#pragma unroll
+      for (int k3 = 0; k3 < M3; ++k3)
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) v[k3][k2] = at(min(t3lo + k3, t3hi), min(t2lo + k2, t2hi));
+#pragma unroll
+      for (int k3 = 0; k3 < M3; ++k3)
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) s = (t3lo + k3 <= t3hi && t2lo + k2 <= t2hi) ? s + v[k3][k2] : s;
+    } else {
+      for (int t3 = t3lo; t3 <= t3hi; ++t3)
+        for (int t2 = t2lo; t2 <= t2hi; ++t2) s += at(t3, t2);
+    }
     y[i] = s;
     dot = x[i] * s;
   }
@@ -420,13 +441,14 @@ __device__ __forceinline__ void combine_body(const double* __restrict__ ext, con
   }
 }
 
+template <int M3, int M2>
 __global__ __launch_bounds__(kBlock) void k_spmv_combine(const double* __restrict__ ext,
                                                          const double* __restrict__ x, double* __restrict__ y,
                                                          int n1, int n2, int n3, int P, int B2, int B3, int T2,
                                                          int T3, long long N, double* __restrict__ partial,
                                                          const int* __restrict__ flag) {
   if (flag && *flag) return;
-  combine_body(ext, x, y, n1, n2, n3, P, B2, B3, T2, T3, N, partial, (int)blockIdx.x);
+  combine_body<M3, M2>(ext, x, y, n1, n2, n3, P, B2, B3, T2, T3, N, partial, (int)blockIdx.x);
 }
 
 struct CombineJob {
@@ -444,8 +466,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_combine_g(const CombineJob* __r
   const int j = group_job(start, njobs, (int)blockIdx.x);
   const CombineJob& t = jobs[j];
   if (t.flag && *t.flag) return;
-  combine_body(t.ext, t.x, t.y, t.n1, t.n2, t.n3, t.P, t.B2, t.B3, t.T2, t.T3, t.N, t.partial,
-               (int)blockIdx.x - start[j]);
+  combine_body<0, 0>(t.ext, t.x, t.y, t.n1, t.n2, t.n3, t.P, t.B2, t.B3, t.T2, t.T3, t.N, t.partial,
+                     (int)blockIdx.x - start[j]);
 }
 
 template <int D, int P, int R>
@@ -542,8 +564,22 @@ igafd_status launch_tile(igafd_ctx* c, const double* xpad, double* y, double* pa
 #undef IGAFD_CH
   }
   if (s != IGAFD_OK) return s;
-  hipLaunchKernelGGL(k_spmv_combine, dim3(vb), dim3(kBlock), 0, c->stream, c->ext, xpad, y, n1, n2, n3, P, B2, B3,
-                     T2, T3, c->N, partial, flag);
+  // covering tiles per row: at most (E - 1) / B + 1 per direction
+  const int m3 = (B3 + P - 1) / B3 + 1, m2 = (B2 + 2 * P - 1) / B2 + 1;
+#define IGAFD_COMB(M3, M2)                                                                                        \
+  hipLaunchKernelGGL((k_spmv_combine<M3, M2>), dim3(vb), dim3(kBlock), 0, c->stream, c->ext, xpad, y, n1, n2, n3, P, \
+                     B2, B3, T2, T3, c->N, partial, flag)
+  if (m3 <= 2 && m2 <= 2)
+    IGAFD_COMB(2, 2);
+  else if (m3 <= 2 && m2 <= 3)
+    IGAFD_COMB(2, 3);
+  else if (m3 <= 3 && m2 <= 3)
+    IGAFD_COMB(3, 3);
+  else if (m3 <= 2 && m2 <= 6)
+    IGAFD_COMB(2, 6);
+  else
+    IGAFD_COMB(0, 0);
+#undef IGAFD_COMB
   IGAFD_HIP_CHECK(hipGetLastError());
   return IGAFD_OK;
 }
