@@ -68,6 +68,9 @@ TILE_CASES = [
     # 512 threads per block (one block per CU, larger tiles)
     ("3d_warped_kappa_p3", "4x4x512"), ("3d_ring_p2", "2x6x512"), ("3d_warped_p5", "2x2x512"),
     ("long_n1_p3", "4x4x512"),
+    # the combine's unrolled forms: at most 2x2 (identity 4x3), 2x3, 3x3 (ring 8x1) and 2x6
+    # (p = 5, 2x5) covering tiles per row; the loop for the others
+    ("3d_warped_p5", "2x5x512"),
 ]
 
 
