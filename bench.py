@@ -845,8 +845,9 @@ def main():
            "annulus": run_annulus}[args.workload]
     out = run(args, api, torch, synth)
     if args.workload == "ring" and not args.no_extras:
-        # the two other comparisons the benchmark spec names, on their own workloads
-        # (fewer timed solves; each sub-object carries its own config)
+        # the two extensions' comparisons (mixed-precision FD on the warped
+        # cube, learned scaling), on their own workloads (fewer timed solves;
+        # each sub-object carries its own config)
         sub = argparse.Namespace(**vars(args))
         sub.steps, sub.warmup, sub.elements, sub.degree = max(3, args.steps // 4), 1, 0, 0
         log("== warped cube, p = 5, 96^3: BF16 / split-BF16 / FP32 / FP64 FD")

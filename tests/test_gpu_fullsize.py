@@ -128,8 +128,8 @@ def test_thick_ring_128_p3(api):
         # split BF16: BF16's 5e-2 scaled by the per-product bounds, 3 * 2^-16 against 2^-8
         e3 = check_fd(api, ctx, F, "bf16x3", 6e-4, 3)
         assert e3 * 30 < check_fd(api, ctx, F, "bf16", 5e-2, 3)
-        # the FP64 solve against the oracle's solve: the benchmark spec's 1e-7 at a
-        # 1e-8 residual, iterations within one
+        # the FP64 solve against the oracle's solve: within 1e-7 at a 1e-8
+        # residual, iterations within one
         u = to_dev(np.zeros(ctx.N))
         info = api.igafd_solve(ctx, b, u)
         assert info["status"] == "OK" and info["true_relres"] <= 1e-8
