@@ -177,7 +177,7 @@ constexpr int kTileMaxChP[kMaxDegree + 1] = {0, 8, 8, 8, 4, 1, 1};
 // (fewer address operations); at p = 4 three chunks would spill 244.
 constexpr int kXsRegMaxChP[kMaxDegree + 1] = {0, 8, 4, 5, 2, 1, 1};
 
-// chunks of 256 row pairs of a B2 x B3 tile
+// chunks of tb row pairs (one per thread of a tb-thread block) of a B2 x B3 tile
 inline int tile_chunks(int b2, int b3, int n1, int tb = kBlock) { return ((b2 * b3 * n1 + 1) / 2 + tb - 1) / tb; }
 
 typedef const __attribute__((address_space(1))) char* gbytes;  // global memory, byte addressed
@@ -289,9 +289,10 @@ __device__ __forceinline__ void tile_pair(int o2, int o3, const double* __restri
 // band, x: row 0 of plane 0 / of the zero-halo vector; ext: T2*T3 tiles of
 // E2*E3*n1 values (E2 = B2+2p, E3 = B3+p), line (e3, e2) = target line
 // (c0+e3, a0+e2-p).  LDS: the accumulator plus 128 discard slots.  Row pair
-// q = threadIdx.x + 256 m of the tile: rows 2q, 2q+1 of the concatenated runs.
-// The LDS tile allows about two blocks per CU: the occupancy target lets the
-// scheduler keep a chunk's loads in flight together.
+// q = threadIdx.x + TB m of the tile: rows 2q, 2q+1 of the concatenated runs.
+// Two waves per SIMD (two 256-thread blocks or one 512-thread block per CU):
+// the occupancy target lets the scheduler keep a chunk's loads in flight
+// together.
 // tile_body: the work of tile `tile` (t2 fastest) by TB threads.
 template <int P, int CH, int TB>
 __device__ __forceinline__ void tile_body(const double* __restrict__ band, long long Ns, const double* __restrict__ x,
@@ -390,14 +391,13 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 
 __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
-// y[i] = sum over the tiles whose extended region holds row i (t3, then t2
-// ascending); optional per-block partial of (x, y).  Block bx of the rows.
-// Per row, the tiles whose extended region covers it: t3 in [t3lo, t3hi] and
-// t2 in [t2lo, t2hi]; their accumulator values are added in the order t3, t2
-// ascending.  M3, M2 > 0: at most M3 x M2 covering tiles (the launch's tile
-// shape guarantees it), all of their loads issued before the first add
-// (slots past the row's range read a covered tile and are skipped by a
-// select, so the sum and its order are those of the loop); 0, 0: the loop.
+// y[i] = sum over the tiles whose extended region holds row i (t3 in [t3lo,
+// t3hi], t2 in [t2lo, t2hi]; added in the order t3, then t2 ascending);
+// optional per-block partial of (x, y).  Block bx of the rows.  M3, M2 > 0:
+// at most M3 x M2 covering tiles (the launch's tile shape guarantees it), all
+// of their loads issued before the first add (slots past the row's range read
+// a covered tile and are skipped by a select, so the sum and its order are
+// those of the loop); 0, 0: the loop.
 template <int M3, int M2>
 __device__ __forceinline__ void combine_body(const double* __restrict__ ext, const double* __restrict__ x,
                                              double* __restrict__ y, int n1, int n2, int n3, int P, int B2, int B3,
