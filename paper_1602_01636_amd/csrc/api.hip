@@ -1613,8 +1613,16 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
       b2 = std::atoi(e);
       b3 = std::atoi(e3);
       if (std::strchr(e3, 'x')) tb = std::atoi(std::strchr(e3, 'x') + 1);
-    } else if (!(e && std::atoi(e) == 0) && !spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
-      b2 = b3 = 0;
+    } else if (!(e && std::atoi(e) == 0)) {
+      int dev = 0, maxlds = 0;
+      IGAFD_HIP_CHECK(hipGetDevice(&dev));
+      IGAFD_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      if (c->p >= 1 && c->p <= 6 && kTile512Default[c->p] &&
+          spmv_pick_tile(c.get(), std::min(kTile512Lds, (long long)maxlds), &b2, &b3, 512)) {
+        tb = 512;
+      } else if (!spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
+        b2 = b3 = 0;
+      }
     }
     if ((s = spmv_set_tile(c.get(), b2, b3, tb)) != IGAFD_OK) return s;
   }

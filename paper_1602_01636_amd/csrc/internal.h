@@ -18,6 +18,12 @@ constexpr int kMaxDegree = 6;
 constexpr int kMaxModes = 16;
 constexpr int kBlock = 256;
 constexpr long long kTileLdsDefault = 80 * 1024;  // two tiled-product blocks per CU (160 KB LDS)
+// Degrees whose setup default is a 512-thread tile (one block per CU, up to
+// kTileLds512 of LDS): measured faster at p = 3 (128^3: 6x6 lines 578 us
+// against 6x3 of 256 threads, 597 us) and p = 5 (96^3: 964 against 1031 us),
+// slower at p = 4 (112^3: every 512-thread shape 907 us or more against 834)
+constexpr bool kTile512Default[kMaxDegree + 1] = {false, false, false, true, false, true, false};
+constexpr long long kTile512Lds = 128 * 1024;
 
 void set_error(const std::string& msg);
 // block partials (per sum) a context's reductions may write; sizes its buffer

@@ -66,10 +66,7 @@ def test_batched_mixed_tile_blocks_equals_individual(api, monkeypatch):
     probs = _batch_problems()
     ctxs = []
     for k, pr in enumerate(probs):
-        if k % 2 == 0:
-            monkeypatch.setenv("IGAFD_SPMV_TILE", "2x2x512")
-        else:
-            monkeypatch.delenv("IGAFD_SPMV_TILE", raising=False)
+        monkeypatch.setenv("IGAFD_SPMV_TILE", "2x2x512" if k % 2 == 0 else "2x2")
         ctxs.append(api.igafd_setup(pr))
     threads = [api.igafd_get_shape(c)["tile_threads"] for c in ctxs]
     assert threads[0::2] == [512] * 3 and all(t == 256 for t in threads[1::2])
