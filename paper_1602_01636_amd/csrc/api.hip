@@ -1617,11 +1617,14 @@ igafd_status setup_impl(const igafd_problem* pr, void* stream, igafd_ctx** out, 
       int dev = 0, maxlds = 0;
       IGAFD_HIP_CHECK(hipGetDevice(&dev));
       IGAFD_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      double s256 = 0.0, s512 = 0.0;
+      int c2 = 0, c3 = 0;
+      if (!spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3, 256, &s256)) b2 = b3 = 0;
       if (c->p >= 1 && c->p <= 6 && kTile512Default[c->p] &&
-          spmv_pick_tile(c.get(), std::min(kTile512Lds, (long long)maxlds), &b2, &b3, 512)) {
+          spmv_pick_tile(c.get(), std::min(kTile512Lds, (long long)maxlds), &c2, &c3, 512, &s512) && s512 > s256) {
+        b2 = c2;
+        b3 = c3;
         tb = 512;
-      } else if (!spmv_pick_tile(c.get(), kTileLdsDefault, &b2, &b3)) {
-        b2 = b3 = 0;
       }
     }
     if ((s = spmv_set_tile(c.get(), b2, b3, tb)) != IGAFD_OK) return s;

@@ -18,10 +18,12 @@ constexpr int kMaxDegree = 6;
 constexpr int kMaxModes = 16;
 constexpr int kBlock = 256;
 constexpr long long kTileLdsDefault = 80 * 1024;  // two tiled-product blocks per CU (160 KB LDS)
-// Degrees whose setup default is a 512-thread tile (one block per CU, up to
-// kTileLds512 of LDS): measured faster at p = 3 (128^3: 6x6 lines 578 us
-// against 6x3 of 256 threads, 597 us) and p = 5 (96^3: 964 against 1031 us),
-// slower at p = 4 (112^3: every 512-thread shape 907 us or more against 834)
+// Degrees whose setup considers 512-thread tiles (one block per CU, up to
+// kTile512Lds of LDS) beside the 256-thread ones, keeping the better score of
+// the shape model (whose grid-tail factor favours the smaller tiles on small
+// problems): measured faster at p = 3 (128^3: 6x6 lines 578 us against 6x3 of
+// 256 threads, 597 us) and p = 5 (96^3: 964 against 1031 us), slower at p = 4
+// (112^3: every 512-thread shape 907 us or more against 834)
 constexpr bool kTile512Default[kMaxDegree + 1] = {false, false, false, true, false, true, false};
 constexpr long long kTile512Lds = 128 * 1024;
 
@@ -184,7 +186,8 @@ igafd_status spectral_bounds(igafd_ctx* c, double* qmin, double* qmax, double* q
 igafd_status spmv(igafd_ctx* c, const double* xpad, double* y, double* partial, const int* flag);
 igafd_status spmv_unpadded(igafd_ctx* c, const double* x, double* y, double* partial, const int* flag);
 int spmv_blocks(const igafd_ctx* c);
-bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3, int tb = 256);
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2, int* b3, int tb = 256,
+                    double* score = nullptr);
 igafd_status spmv_set_tile(igafd_ctx* c, int b2, int b3, int tb = 256);
 igafd_status mask_hole(igafd_ctx* c, double* y);
 // fd.hip

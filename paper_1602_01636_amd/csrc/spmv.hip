@@ -602,7 +602,7 @@ int spmv_blocks(const igafd_ctx* c) {
 // grid).  Returns false when no shape fits (or the problem is 2D or too large
 // for 32-bit row offsets): the row-parallel kernel is used then.  tb: threads
 // per block (256: up to two blocks per CU; 512: one).
-bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out, int tb) {
+bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b3_out, int tb, double* score_out) {
   if (c->dim != 3 || c->N >= (1LL << 29)) return false;  // byte offsets of rows fit 32 bits
   const int p = c->p, n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
   int dev = 0, cus = 256, lds_cu = 160 * 1024;
@@ -634,6 +634,7 @@ bool spmv_pick_tile(const igafd_ctx* c, long long lds_limit, int* b2_out, int* b
         *b3_out = b3;
       }
     }
+  if (score_out) *score_out = best;
   return best > 0.0;
 }
 
